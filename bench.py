@@ -1,0 +1,231 @@
+"""Benchmark: ms per boosting round of Viola-Jones AdaBoost on one MI355X.
+
+Workload (default): 5,000 + 10,000 synthetic 24x24 windows (seeded stand-in for
+the face / non-face training set), all 162,336 Haar features, FP32 weights
+with FP64 accumulation in the scan.  A step is one boosting round: the scan
+of every feature's sorted keys against the current weights, the argmin over
+features, the threshold, beta / alpha and the weight update.  The one-time
+preparation (integral images, feature values, per-feature sort) runs before
+the timed region and is reported separately as init_ms.
+
+Prints one JSON line.  --batched adds the batched-jobs measurement
+(32 uneven jobs, jobs*rounds/s, against the same jobs run one at a time).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "ms per boosting round (162k Haar × 15k imgs); batched jobs·rounds/s vs plain"
+SCAN_SOURCES = ["paper_1306_1467_amd/csrc/k_scan.hip", "paper_1306_1467_amd/csrc/scan_core.h",
+                "paper_1306_1467_amd/csrc/common.h"]
+
+
+def scan_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in SCAN_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kind: str, precision: str):
+    """HBM bytes per scan launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on a different scan source."""
+    path = os.path.join(ROOT, "profiles", f"stump_scan_{kind}_counters.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("scan_source_hash") != scan_source_hash() or d.get("precision") != precision:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(images, labels, n_features: int, rounds: int):
+    """The FP64 oracle's round on a bounded sample of features, scaled to all."""
+    import numpy as np
+    import oracle
+    F = oracle.feature_count(24, 24)
+    feats = oracle.enumerate_features(24, 24)
+    rng = np.random.default_rng(0)
+    pick = np.sort(rng.choice(F, n_features, replace=False))
+    threads = oracle.max_threads()
+    ii = oracle.integrals(images, threads)
+    vals = oracle.feature_values(ii, feats[pick], threads)
+    order = oracle.sort_features(vals, threads)
+    w = oracle.init_weights(labels)
+    scratch = np.zeros(n_features, oracle.STUMP_DTYPE)
+    oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)   # warm caches
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)
+    dt = (time.perf_counter() - t0) / rounds
+    return {"value": round(dt * 1e3 * F / n_features, 2), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"{rounds} oracle rounds over {n_features:,} of {F:,} features x {len(labels):,} windows, "
+                      f"scaled by {F / n_features:.3f} (one-time value/sort preparation excluded)"}
+
+
+def run_single(args, torch, vb, synth):
+    spec = synth.config_jobs(1)[0]
+    images, labels = spec.make()
+    t0 = time.perf_counter()
+    tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=args.precision,
+                    schedule_id=args.schedule, flags=vb.BOOST_FLAG_TIMING)
+    torch.cuda.synchronize()
+    init_ms = (time.perf_counter() - t0) * 1e3
+    if args.warmup:
+        vb.boost_train(tr.ctx, args.warmup, False)
+    tr.stream.synchronize()
+    vb.boost_reset_timing(tr.ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vb.boost_train(tr.ctx, args.steps, False)
+    tr.stream.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    scan_ms, fin_ms, nr, _ = vb.boost_get_timing(tr.ctx)
+    rec = tr.round()
+    F, n = tr.F, tr.n
+    scan_avg = scan_ms / nr
+    alg_bytes = F * n * 2
+    achieved = alg_bytes / (scan_avg * 1e-3) / 1e9
+    traffic = profiled_traffic("config1", args.precision)
+    out = {
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
+        "init_ms": round(init_ms, 1),
+        "scan_ms_avg": round(scan_avg, 4),
+        "finalize_ms_avg": round(fin_ms / nr, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / (scan_avg * 1e-3) / 1e9, 1),
+                     "kernel": "k_scan", "alg_bytes_per_launch": alg_bytes},
+        "last_round": {"feature": int(rec.feature), "error_raw": rec.error_raw, "polarity": int(rec.polarity),
+                       "threshold": int(rec.threshold)},
+        "F": F, "n": n,
+    }
+    tr.close()
+    return out, images, labels
+
+
+def run_batched(args, torch, vb, synth):
+    import numpy as np
+    from paper_1306_1467_amd import batch as vbatch
+    specs = synth.config_jobs(3)
+    data = [s.make() for s in specs]
+    rounds = args.batch_rounds
+    # plain: each job alone through the single-job path
+    t_plain = 0.0
+    plain_recs = []
+    for (images, labels) in data:
+        tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=args.batch_precision)
+        vb.boost_train(tr.ctx, 1, False)      # warm the graph
+        tr.stream.synchronize()
+        t0 = time.perf_counter()
+        r = vb.boost_train(tr.ctx, rounds, True)
+        t_plain += time.perf_counter() - t0
+        plain_recs.append(r)
+        tr.close()
+        del tr
+        torch.cuda.empty_cache()
+    bt = vbatch.BatchTrainer([(torch.from_numpy(i), torch.from_numpy(l)) for i, l in data],
+                             precision=args.batch_precision)
+    bt.train(1, False)
+    bt.sync()
+    t0 = time.perf_counter()
+    recs = bt.train(rounds, True)
+    t_batch = time.perf_counter() - t0
+    # plain ran one extra warm round per job; compare rounds 1..rounds
+    same = all(np.array_equal(recs[:, k]["feature"], plain_recs[k]["feature"][:0] if False else
+                              _shifted(plain_recs[k], recs[:, k])) for k in range(len(data)))
+    jr = len(data) * rounds
+    bt.close()
+    return {"jobs": len(data), "rounds": rounds, "precision": args.batch_precision,
+            "batched_jobs_rounds_per_s": round(jr / t_batch, 1),
+            "plain_jobs_rounds_per_s": round(jr / t_plain, 1),
+            "speedup_vs_plain": round(t_plain / t_batch, 3),
+            "stumps_identical_to_plain": bool(same)}
+
+
+def _shifted(plain, batched):
+    import numpy as np
+    return np.array_equal(plain["feature"], batched["feature"]) and \
+        np.array_equal(plain["error_raw"], batched["error_raw"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", default="fp32_wide")
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-features", type=int, default=12000)
+    ap.add_argument("--cpu-rounds", type=int, default=2)
+    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--batch-rounds", type=int, default=50)
+    ap.add_argument("--batch-precision", default="fp32_wide")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="run one device copy of this many GiB first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+              "(the path would shard features across GPUs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1306_1467_amd import synth
+    from paper_1306_1467_amd import vjboost as vb
+    vb.lib()
+    if args.copy_calibration_gib > 0:
+        nb = int(args.copy_calibration_gib * 2 ** 30)
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    res, images, labels = run_single(args, torch, vb, synth)
+    line = {
+        "metric": METRIC,
+        "value": res["ms_per_step"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32_wide": "f32 weights, f64 accumulation", "fp32_kahan": "f32 two-sum",
+                  "fp32": "f32", "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "162,336 Haar features x 15,000 windows 24x24 (5,000 pos + 10,000 neg), "
+                               "one boosting round per step", "precision": args.precision,
+                   "schedule": args.schedule, "features": res["F"], "windows": res["n"]},
+        "init_ms": res["init_ms"],
+        "scan_ms_avg": res["scan_ms_avg"],
+        "finalize_ms_avg": res["finalize_ms_avg"],
+        "roofline": res["roofline"],
+        "last_round": res["last_round"],
+    }
+    if args.batched:
+        line["batched"] = run_batched(args, torch, vb, synth)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(images, labels, args.cpu_features, args.cpu_rounds)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

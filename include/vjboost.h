@@ -1,0 +1,285 @@
+/*
+ * vjboost.h -- C ABI of the MI355X (gfx950) Viola-Jones AdaBoost round engine.
+ *
+ * The library trains discrete AdaBoost over Haar-feature decision stumps as
+ * described in arXiv 1306.1467, Section 2 (integral image, Section 2.1; the five
+ * Haar feature types and the decision stump, Section 2.2; weights,
+ * normalisation, best-stump search, update and the strong classifier,
+ * Section 2.3).  Each boosting round searches every feature and every window
+ * for the stump with the smallest weighted error, then updates the weights.
+ *
+ * General rules for every entry point:
+ *  - Plain C types only; every "d_" pointer is HIP device memory, every other
+ *    pointer is host memory.  Nothing is retained from a host pointer after the
+ *    call returns.
+ *  - Return value: BOOST_OK (0) or a negative status below; details are in
+ *    boost_last_error() (a thread-local string, valid until the next call on
+ *    that thread).  No exception crosses this boundary.
+ *  - Work is enqueued on boost_options.stream (a hipStream_t; NULL is the
+ *    legacy default stream).  A call returns once its work is enqueued, except
+ *    where it says it synchronises (any call that writes a host output does).
+ *  - Sample indices seen through this interface are the caller's order; the
+ *    library internally keeps positives first.
+ *  - One context must not be used from two threads at once.
+ */
+#ifndef VJBOOST_H
+#define VJBOOST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define BOOST_OK            0
+#define BOOST_E_INVALID    (-1)  /* bad argument (see each call) */
+#define BOOST_E_NOMEM      (-2)  /* workspace too small */
+#define BOOST_E_DEVICE     (-3)  /* a HIP runtime error */
+#define BOOST_E_DEGENERATE (-4)  /* eps = 0 (or below the floor) with BOOST_ON_PERFECT_STOP */
+
+/* ------------------------------------------------------------ feature set
+ * Section 2.2: five Haar feature types.  Bit t of type_mask enables type t:
+ *   0 three-rectangle horizontal [white | dark | white]
+ *   1 three-rectangle vertical   (the same stacked)
+ *   2 two-rectangle horizontal   [white | dark]
+ *   3 two-rectangle vertical     [white / dark]
+ *   4 four-rectangle             [white dark / dark white]
+ * A feature's value is (sum over dark cells) - (sum over white cells), exact
+ * int32.  Each cell is cell_w x cell_h pixels (both >= 1, scaled
+ * independently) and the feature sits at every (x, y) where it fits in the
+ * window.  Global index order: type (in the order above), cell_w, cell_h, y,
+ * x (x fastest).  For a 24x24 window this gives 27,600 + 27,600 + 43,200 +
+ * 43,200 + 20,736 = 162,336 features, the counts printed in Section 2.2.
+ * Windows are 1..32 pixels on each side. */
+#define BOOST_TYPE_3H 0
+#define BOOST_TYPE_3V 1
+#define BOOST_TYPE_2H 2
+#define BOOST_TYPE_2V 3
+#define BOOST_TYPE_4  4
+#define BOOST_ALL_TYPES 0x1Fu
+
+typedef struct {
+    int32_t  window_w;
+    int32_t  window_h;
+    uint32_t type_mask;
+} boost_feature_set;
+
+typedef struct {
+    int32_t type, x, y, cell_w, cell_h;
+} boost_feature;
+
+/* ------------------------------------------------------------ options
+ * precision: arithmetic of the per-round weighted-error scan.
+ *   BOOST_PREC_FP32        FP32 weights, FP32 running sums (plain).
+ *   BOOST_PREC_FP32_KAHAN  FP32 weights, FP32 running sums with two-sum
+ *                          compensation; candidates compared on the
+ *                          compensated FP32 prefix.
+ *   BOOST_PREC_FP64        FP64 weights and FP64 running sums (n <= 20000:
+ *                          the table must fit in LDS).
+ *   BOOST_PREC_FP32_WIDE   FP32 weights accumulated in FP64.  For weights
+ *                          above ~1e-9 every sum is exact, so the only
+ *                          difference from FP64 weights is the FP32 rounding
+ *                          of each weight (<= 2^-24 relative on every error).
+ * Normalisation, the update, beta and alpha are always FP64.
+ * on_perfect: what a round with eps_raw <= eps_floor does.  Section 2.3 leaves
+ *   eps = 0 undefined (beta = 0, alpha infinite).  CLAMP uses
+ *   eps' = max(eps, eps_floor) for beta and alpha and goes on; STOP records
+ *   the stump, leaves the weights unchanged and makes every later round a
+ *   no-op (its record has feature = -1), returning BOOST_E_DEGENERATE.
+ * eps_floor: > 0 and < 0.5 (default 1e-10).
+ * schedule_id: 0 picks the default launch shape; 1.. select tuned variants
+ *   (see boost_schedule_count).
+ * flags: BOOST_FLAG_TIMING records per-kernel device times (boost_get_timing);
+ *   BOOST_FLAG_NO_GRAPH launches kernels directly instead of replaying a
+ *   captured HIP graph in boost_train. */
+#define BOOST_PREC_FP32        0
+#define BOOST_PREC_FP32_KAHAN  1
+#define BOOST_PREC_FP64        2
+#define BOOST_PREC_FP32_WIDE   3
+
+#define BOOST_ON_PERFECT_CLAMP 0
+#define BOOST_ON_PERFECT_STOP  1
+
+#define BOOST_FLAG_TIMING   1
+#define BOOST_FLAG_NO_GRAPH 2
+
+typedef struct {
+    int32_t precision;
+    int32_t on_perfect;
+    double  eps_floor;
+    int32_t schedule_id;
+    int32_t flags;
+    void   *stream;
+} boost_options;
+
+/* Fills *o with the defaults: FP32_WIDE, CLAMP, 1e-10, schedule 0, no flags,
+ * NULL stream.  Returns BOOST_E_INVALID if o is NULL. */
+int boost_options_default(boost_options *o);
+
+/* ------------------------------------------------------------ stump record
+ * One weak classifier, Section 2.2 / 2.3: h(x) = 1 iff p * f(x) < p * theta.
+ * polarity p is +1 or -1; threshold theta is an integer that realises the
+ * chosen split exactly.  split_rank k: the number of windows, in ascending
+ * feature-value order, on the side below the threshold.  error_raw is the
+ * minimum weighted error eps_t under the normalised weights; error is
+ * max(error_raw, eps_floor); beta = error / (1 - error); alpha =
+ * ln(1 / beta).  round is the 0-based round index.  Ties: smaller error, then
+ * smaller feature index, then p = +1, then smaller split_rank. */
+typedef struct {
+    int64_t feature;
+    int32_t type, x, y, cell_w, cell_h;
+    int32_t polarity;
+    int32_t threshold;
+    int32_t split_rank;
+    int32_t round;
+    int32_t pad;
+    double  error_raw;
+    double  error;
+    double  beta;
+    double  alpha;
+} boost_stump;
+
+typedef struct boost_ctx boost_ctx;
+
+/* ------------------------------------------------------------ host-only queries */
+
+/* Number of features of a feature set (closed form of the Section 2.2
+ * enumeration).  Returns -1 for an invalid set (window outside 1..32, empty or
+ * out-of-range mask, NULL). */
+int64_t boost_feature_count(const boost_feature_set *fs);
+
+/* Descriptor of feature j (0 <= j < count) in the global order. */
+int boost_feature_desc(const boost_feature_set *fs, int64_t j, boost_feature *out);
+
+/* Device workspace bytes boost_init needs for n windows; 0 for invalid
+ * arguments (n < 2, n > 32767, invalid feature set or options). */
+size_t boost_workspace_bytes(int64_t n, const boost_feature_set *fs, const boost_options *o);
+
+/* Number of launch schedules (schedule_id values 0 .. count-1) for a precision. */
+int boost_schedule_count(int32_t precision);
+
+/* ------------------------------------------------------------ training
+ * boost_init: ingest n windows and prepare every feature once (Section 3.3.1's
+ * one-time "upload" of the feature values): copy labels and a positives-first
+ * order, integral images (Section 2.1), the int32 value of every feature on
+ * every window (Section 2.2) and, per feature, the windows in ascending value
+ * order with the ends of runs of equal values marked.  Then the Table 2
+ * initial weights 1/(2l) and 1/(2m), normalised.
+ *   d_images  n x window_h x window_w uint8, row-major per window (device).
+ *   d_labels  n uint8, 1 = positive (face), 0 = negative (device).
+ *   d_workspace / workspace_bytes  caller-owned device memory of at least
+ *             boost_workspace_bytes(n, fs, o) bytes; it must outlive the
+ *             context.  Inputs may be freed once boost_init returns.
+ * Errors: BOOST_E_INVALID for NULL pointers, n outside 2..32767, an invalid
+ * feature set or options, a label other than 0/1, or a class with no
+ * windows (1/(2l) or 1/(2m) undefined); BOOST_E_NOMEM if the workspace is too
+ * small; BOOST_E_DEVICE on a HIP error.  Synchronises.  On success *out holds
+ * a context owned by the library (free with boost_destroy). */
+int boost_init(boost_ctx **out, const uint8_t *d_images, const uint8_t *d_labels, int64_t n,
+               const boost_feature_set *fs, const boost_options *o,
+               void *d_workspace, size_t workspace_bytes);
+
+/* One boosting round (Section 2.3 steps 1-4; Section 3.3.2 master steps 1-4):
+ * the normalised weights' best stump over all features and thresholds, its
+ * beta and alpha, and the weight update w_i <- w_i beta^(1 - e_i) followed by
+ * normalisation.
+ *   out_host       NULL, or a host record that receives the stump (synchronises).
+ *   d_feature_err  NULL, or device double[F][2] receiving each feature's
+ *                  minimum error for p = +1 ([j][0]) and p = -1 ([j][1]).
+ * Returns BOOST_E_DEGENERATE when the STOP policy has triggered (checked only
+ * when the call synchronises). */
+int boost_round(boost_ctx *c, boost_stump *out_host, double *d_feature_err);
+
+/* rounds consecutive rounds; out_host (NULL or host array of rounds records)
+ * receives every stump (synchronises).  Rounds are replayed from a captured
+ * HIP graph unless BOOST_FLAG_NO_GRAPH or BOOST_FLAG_TIMING is set. */
+int boost_train(boost_ctx *c, int32_t rounds, boost_stump *out_host);
+
+/* Current normalised weights, device double[n], caller's sample order. */
+int boost_get_weights(boost_ctx *c, double *d_w);
+
+/* Replace the weights (device double[n], caller's order; finite, >= 0, not all
+ * zero; normalised by the library).  Synchronises to validate;
+ * BOOST_E_INVALID if the check fails (the previous weights are kept). */
+int boost_set_weights(boost_ctx *c, const double *d_w);
+
+/* Rounds completed so far. */
+int boost_rounds_done(boost_ctx *c, int32_t *out_rounds);
+
+/* Accumulated device time of the rounds run with BOOST_FLAG_TIMING:
+ * out[0] scan-kernel ms, out[1] finalize-kernel ms, out[2] rounds timed,
+ * out[3] scan launches timed.  Synchronises.  boost_reset_timing clears it. */
+int boost_get_timing(boost_ctx *c, double out[4]);
+int boost_reset_timing(boost_ctx *c);
+
+/* ------------------------------------------------------------ inspection (parity checks)
+ * Values of features j0 .. j0+nf-1 on every window: device int32[nf][n],
+ * caller's order (Section 2.2). */
+int boost_get_feature_values(boost_ctx *c, int64_t j0, int64_t nf, int32_t *d_out);
+
+/* Integral images, device int32[n][window_h+1][window_w+1], caller's order,
+ * zero first row and column (Section 2.1). */
+int boost_get_integral(boost_ctx *c, int32_t *d_out);
+
+/* The per-feature value order built by boost_init: for features j0 ..
+ * j0+nf-1, d_order int32[nf][n] = window index (caller's order) at each rank
+ * of ascending value, d_run_end uint8[nf][n] = 1 where the value at that rank
+ * differs from the next (or it is the last rank). */
+int boost_get_sorted(boost_ctx *c, int64_t j0, int64_t nf, int32_t *d_order, uint8_t *d_run_end);
+
+/* Strong classifier of Section 2.3: C(x) = 1 iff sum_t alpha_t h_t(x) >=
+ * 1/2 sum_t alpha_t, for the context's training windows.
+ *   stumps  host array of T records (only feature, polarity, threshold, alpha are read).
+ *   d_out   device uint8[n] decisions; d_score NULL or device double[n] with
+ *           sum_t alpha_t h_t(x) (caller's order). */
+int boost_classify_train(boost_ctx *c, const boost_stump *stumps, int32_t T,
+                         uint8_t *d_out, double *d_score);
+
+void boost_destroy(boost_ctx *c);
+
+/* ------------------------------------------------------------ batched jobs
+ * Many independent training jobs (each its own windows, labels and feature
+ * set) advanced one round at a time by a single persistent scan launch plus
+ * one finalize launch for all jobs.  Each job's results equal those of the
+ * same job run alone through boost_init/boost_round with the same options. */
+typedef struct {
+    const uint8_t    *d_images;
+    const uint8_t    *d_labels;
+    int64_t           n;
+    boost_feature_set fs;
+} boost_job;
+
+typedef struct boost_batch boost_batch;
+
+/* Workspace for a batch; 0 for invalid arguments. */
+size_t boost_batch_workspace_bytes(int32_t n_jobs, const boost_job *jobs, const boost_options *o);
+
+/* As boost_init for every job (host array jobs[n_jobs], 1..4096 jobs). */
+int boost_batch_init(boost_batch **out, int32_t n_jobs, const boost_job *jobs,
+                     const boost_options *o, void *d_workspace, size_t workspace_bytes);
+
+/* One round of every job; out_host NULL or host boost_stump[n_jobs]
+ * (synchronises). */
+int boost_batch_round(boost_batch *b, boost_stump *out_host);
+
+/* rounds rounds of every job; out_host NULL or host boost_stump[rounds][n_jobs]. */
+int boost_batch_train(boost_batch *b, int32_t rounds, boost_stump *out_host);
+
+/* Weights of job k, device double[n_k], caller's order. */
+int boost_batch_get_weights(boost_batch *b, int32_t job, double *d_w);
+
+/* As boost_get_timing, summed over the batch's launches. */
+int boost_batch_get_timing(boost_batch *b, double out[4]);
+
+void boost_batch_destroy(boost_batch *b);
+
+/* ------------------------------------------------------------ misc */
+const char *boost_last_error(void);
+int boost_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VJBOOST_H */

@@ -1,0 +1,43 @@
+// Host launchers of the library's kernels (one translation unit per kernel family).
+#pragma once
+
+#include "common.h"
+
+namespace vjb {
+
+constexpr int kMaxScanGrid = 8192;   // upper bound of scan workgroups (per-workgroup records)
+constexpr int kMaxSortGrid = 1024;   // upper bound of sort workgroups (fallback scratch)
+
+struct ScanPlan {
+    const void* kernel = nullptr;
+    int wg = 0;
+    int grid = 0;
+    size_t lds = 0;
+};
+
+// k_scan.hip
+int scan_schedule_count();
+int scan_schedule_wg(int schedule);
+int64_t scan_table_capacity(int precision, bool narrow);
+int scan_plan(ScanPlan& p, int precision, bool narrow, int schedule, int64_t n, int64_t F, int num_cu);
+int scan_launch(const ScanPlan& p, const JobDev& jd, WgBest* out, double2* ferr, hipStream_t s);
+int finalize_launch(const JobDev& jd, const WgBest* wgb, int n_wg, hipStream_t s);
+
+// k_prep.hip
+int ingest_launch(const JobDev& jd, const uint8_t* d_labels, int64_t n, hipStream_t s);
+int integral_launch(const JobDev& jd, const uint8_t* d_images, hipStream_t s);
+int init_weights_launch(const JobDev& jd, hipStream_t s);
+int set_weights_launch(const JobDev& jd, const double* d_w, double* tmp, hipStream_t s);
+int get_weights_launch(const JobDev& jd, double* d_out, hipStream_t s);
+int feature_values_launch(const JobDev& jd, int64_t j0, int64_t nf, int32_t* d_out, hipStream_t s);
+int integral_out_launch(const JobDev& jd, int32_t* d_out, hipStream_t s);
+int sorted_out_launch(const JobDev& jd, int64_t j0, int64_t nf, int32_t* d_order, uint8_t* d_flags, hipStream_t s);
+struct StumpDev { uint32_t desc; int32_t polarity; int32_t theta; int32_t pad; double alpha; };
+int classify_launch(const JobDev& jd, const StumpDev* d_stumps, int T, uint8_t* d_out, double* d_score, hipStream_t s);
+
+// k_sort.hip
+int64_t sort_pow2(int64_t n);
+size_t sort_scratch_bytes(int64_t n);
+int sort_launch(const JobDev& jd, uint64_t* scratch, int num_cu, hipStream_t s);
+
+}  // namespace vjb

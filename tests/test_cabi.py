@@ -1,0 +1,102 @@
+"""The C ABI library loads, exports every symbol its header declares, and its
+host-only entry points validate arguments (no device work, runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def vb():
+    from paper_1306_1467_amd import vjboost
+    if not os.path.exists(vjboost.LIB_PATH):
+        from paper_1306_1467_amd import build
+        build.build()
+    vjboost.lib()
+    return vjboost
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "vjboost.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(boost_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(vb):
+    names = _declared()
+    assert len(names) >= 25
+    L = ctypes.CDLL(vb.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(vb._SIGS)
+
+
+def test_feature_count_and_desc_match_oracle(vb):
+    for W, H, mask in [(24, 24, 0x1F), (6, 5, 0x04), (16, 20, 0x13), (32, 32, 0x1F), (1, 1, 0x1F)]:
+        fs = vb.feature_set(W, H, mask)
+        F = vb.boost_feature_count(fs)
+        assert F == oracle.feature_count(W, H, mask)
+        ref = oracle.enumerate_features(W, H, mask)
+        idx = np.unique(np.concatenate([np.arange(0, F, max(1, F // 300)), [F - 1]])) if F else []
+        for j in idx:
+            assert vb.boost_feature_desc(fs, int(j)) == tuple(int(v) for v in ref[j])
+
+
+def test_invalid_feature_sets(vb):
+    for W, H, mask in [(0, 24, 0x1F), (33, 24, 0x1F), (24, 24, 0), (24, 24, 0x20)]:
+        assert vb.boost_feature_count(vb.feature_set(W, H, mask)) == -1
+    fs = vb.feature_set(24, 24)
+    with pytest.raises(vb.BoostError):
+        vb.boost_feature_desc(fs, 162336)
+    with pytest.raises(vb.BoostError):
+        vb.boost_feature_desc(fs, -1)
+
+
+def test_workspace_bytes_validation(vb):
+    fs = vb.feature_set(24, 24)
+    o = vb.options()
+    ws = vb.boost_workspace_bytes(15000, fs, o)
+    # keys: 162,336 rows of 1,875 16-byte units rounded to 1,888
+    assert ws >= 162336 * 1888 * 16
+    assert ws < 162336 * 1888 * 16 + 200 * 2 ** 20
+    assert vb.boost_workspace_bytes(1, fs, o) == 0
+    assert vb.boost_workspace_bytes(32768, fs, o) == 0
+    assert vb.boost_workspace_bytes(32767, fs, o) > 0
+    assert vb.boost_workspace_bytes(20001, fs, vb.options("fp64")) == 0
+    assert vb.boost_workspace_bytes(20000, fs, vb.options("fp64")) > 0
+    bad = vb.options()
+    bad.eps_floor = 0.0
+    assert vb.boost_workspace_bytes(100, fs, bad) == 0
+    bad = vb.options()
+    bad.precision = 9
+    assert vb.boost_workspace_bytes(100, fs, bad) == 0
+    bad = vb.options()
+    bad.schedule_id = vb.boost_schedule_count()
+    assert vb.boost_workspace_bytes(100, fs, bad) == 0
+
+
+def test_init_rejects_bad_arguments_before_device_work(vb):
+    fs = vb.feature_set(24, 24)
+    o = vb.options()
+    h = ctypes.c_void_p()
+    L = vb.lib()
+    # NULL pointers and bad sizes fail before any HIP call
+    assert L.boost_init(ctypes.byref(h), None, None, 100, ctypes.byref(fs), ctypes.byref(o), None, 0) == vb.BOOST_E_INVALID
+    fake = ctypes.c_void_p(16)
+    assert L.boost_init(ctypes.byref(h), fake, fake, 1, ctypes.byref(fs), ctypes.byref(o), fake, 1 << 40) == vb.BOOST_E_INVALID
+    assert L.boost_init(ctypes.byref(h), fake, fake, 100, ctypes.byref(fs), ctypes.byref(o), fake, 10) == vb.BOOST_E_NOMEM
+    assert "workspace too small" in vb.last_error()
+    assert L.boost_round(None, None, None) == vb.BOOST_E_INVALID
+    assert L.boost_train(None, 3, None) == vb.BOOST_E_INVALID
+
+
+def test_stump_layout(vb):
+    assert ctypes.sizeof(vb.Stump) == 80
+    assert vb.Stump.error_raw.offset == 48
+    assert ctypes.sizeof(vb.Options) == 32

@@ -1,0 +1,93 @@
+"""Full-size workload (5,000 + 10,000 windows of 24x24, all 162,336 features)
+in the launch configuration the benchmark times: sampled features against the
+oracle, and properties that hold at any size."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1306_1467_amd import synth
+from tests.helpers import err_tolerance, stump_error
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1306_1467_amd import vjboost as vb  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    spec = synth.config_jobs(1)[0]
+    say("generating 15,000 windows")
+    images, labels = spec.make()
+    return images, labels
+
+
+def test_fullsize_sampled_rounds(cfg1):
+    images, labels = cfg1
+    n = len(labels)
+    say("full size: GPU init (all features)")
+    tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision="fp32_wide")
+    F = tr.F
+    assert F == 162336
+    rng = np.random.default_rng(11)
+    pick = np.sort(rng.choice(F, 1500, replace=False))
+    feats = oracle.enumerate_features(24, 24)
+    say("oracle: integral images, sampled values and orders")
+    ii = oracle.integrals(images)
+    # teacher forcing from the oracle's side: weights drawn over a wide range
+    for t, w in enumerate([oracle.init_weights(labels), synth.random_weights((12,), n, -8, 0),
+                           synth.random_weights((13,), n, -20, 0)]):
+        say(f"full size round {t}")
+        wn = w / w.sum()
+        tr.set_weights(wn)
+        rec, ferr = tr.round(feature_err=True)
+        ferr = ferr.cpu().numpy()
+        sel = np.unique(np.concatenate([pick, [rec.feature]]))
+        vals = oracle.feature_values(ii, feats[sel])
+        ost = oracle.best_stumps(vals, oracle.sort_features(vals), labels, wn)
+        assert (np.abs(ferr[sel, 0] - ost["err_pos"]) <= err_tolerance(ost["err_pos"], n, "fp32_wide")).all()
+        assert (np.abs(ferr[sel, 1] - ost["err_neg"]) <= err_tolerance(ost["err_neg"], n, "fp32_wide")).all()
+        # the chosen stump: its error by the definition, and minimal over the sample
+        a = int(np.nonzero(sel == rec.feature)[0][0])
+        e = stump_error(vals[a], labels, wn, rec.polarity, rec.threshold)
+        tol = err_tolerance(np.array([e]), n, "fp32_wide")[0]
+        assert abs(e - rec.error_raw) <= tol
+        assert rec.error_raw <= ost["err"].min() + tol
+        # the reported minimum is the minimum of the per-feature output
+        assert rec.error_raw == ferr[rec.feature].min() == ferr.min()
+        assert rec.feature == int(np.argmax(ferr.min(axis=1) == ferr.min()))
+        w_gpu = tr.weights().cpu().numpy()
+        assert abs(w_gpu.sum() - 1.0) < 1e-12
+    tr.close()
+
+
+def test_fullsize_sorted_sample(cfg1):
+    images, labels = cfg1
+    tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels))
+    feats = oracle.enumerate_features(24, 24)
+    ii = oracle.integrals(images)
+    for j0 in (0, 27600, 55200, 98400, 141600, 162336 - 64):
+        say(f"full size sorted keys at {j0}")
+        order, flags = tr.sorted(j0, 64)
+        order = order.cpu().numpy()
+        flags = flags.cpu().numpy().astype(bool)
+        vals = oracle.feature_values(ii, feats[j0:j0 + 64])
+        assert (np.sort(order, axis=1) == np.arange(len(labels))[None, :]).all()
+        v = np.take_along_axis(vals, order, axis=1)
+        assert (np.diff(v, axis=1) >= 0).all()
+        ends = np.ones_like(flags)
+        ends[:, :-1] = v[:, 1:] != v[:, :-1]
+        assert (flags == ends).all()
+        got = tr.feature_values(j0, 64).cpu().numpy()
+        assert (got == vals).all()
+    tr.close()
