@@ -30,7 +30,7 @@ bool valid_options(const boost_options* o) {
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t keys, ii, ftab, w, wtmp, wtab, st, ring, perm, inv, wgbest, cls, scratch, total;
+    size_t keys, ii, ftab, w, wtmp, wpart, st, ring, perm, inv, wgbest, cls, pad, scratch, total;
 };
 
 static bool make_layout(int64_t n, const boost_feature_set* fs, Layout& L) {
@@ -43,15 +43,16 @@ static bool make_layout(int64_t n, const boost_feature_set* fs, Layout& L) {
     L.keys = take((size_t)F * (size_t)g.row_units * 16);
     L.ii = take((size_t)P * (size_t)ii_stride_of(n) * 4);
     L.ftab = take((size_t)F * 4);
-    L.w = take((size_t)n * 8);
+    L.w = take((size_t)n * 16);
     L.wtmp = take((size_t)n * 8);
-    L.wtab = take((size_t)(n + 1) * 8);
+    L.wpart = take((size_t)kMaxPart * 8);
     L.st = take(sizeof(JobState));
     L.ring = take((size_t)kRing * sizeof(boost_stump));
     L.perm = take((size_t)n * 4);
     L.inv = take((size_t)n * 4);
     L.wgbest = take((size_t)kMaxScanGrid * sizeof(WgBest));
     L.cls = take((size_t)kMaxClassifyT * sizeof(StumpDev));
+    L.pad = take(16);
     L.scratch = take(sort_scratch_bytes(n));
     L.total = off;
     return true;
@@ -63,7 +64,6 @@ using namespace vjb;
 
 struct boost_ctx {
     JobDev jd;
-    WgBest* wgbest = nullptr;
     double* wtmp = nullptr;
     StumpDev* cls = nullptr;
     uint64_t* scratch = nullptr;
@@ -77,7 +77,7 @@ struct boost_ctx {
     hipGraphExec_t gexec = nullptr;
     std::vector<hipEvent_t> ev;
     double t_scan = 0, t_fin = 0, rounds_timed = 0, scans_timed = 0;
-    int64_t launched = 0;   // finalize launches so far (= device ring cursor)
+    int64_t launched = 0;   // scan launches so far (= device ring cursor)
 };
 
 extern "C" {
@@ -165,7 +165,11 @@ int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels
     jd.ii = (const int32_t*)(ws + L.ii);
     jd.ftab = (const uint32_t*)(ws + L.ftab);
     jd.w = (double*)(ws + L.w);
-    jd.wtab = (void*)(ws + L.wtab);
+    jd.wpart = (double*)(ws + L.wpart);
+    jd.wgb = (WgBest*)(ws + L.wgbest);
+    jd.n_part = (int32_t)((n + kUpdWg - 1) / kUpdWg);
+    jd.pad = (const uint4*)(ws + L.pad);
+    jd.unused = 0;
     jd.st = (JobState*)(ws + L.st);
     jd.ring = (boost_stump*)(ws + L.ring);
     jd.perm = (const int32_t*)(ws + L.perm);
@@ -178,14 +182,16 @@ int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels
     jd.precision = o->precision;
     jd.on_perfect = o->on_perfect;
     jd.eps_floor = o->eps_floor;
-    c->wgbest = (WgBest*)(ws + L.wgbest);
     c->wtmp = (double*)(ws + L.wtmp);
     c->cls = (StumpDev*)(ws + L.cls);
     c->scratch = L.total > L.scratch && sort_scratch_bytes(n) ? (uint64_t*)(ws + L.scratch) : nullptr;
 
     std::vector<uint32_t> ftab((size_t)c->F);
     host_feature_table(fs, ftab.data());
+    const uint32_t pd = pad_dword(jd.g);
+    const uint32_t pad_unit[4] = {pd, pd, pd, pd};
     if (hipMemcpyAsync((void*)jd.ftab, ftab.data(), ftab.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync((void*)jd.pad, pad_unit, 16, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemsetAsync(jd.st, 0, sizeof(JobState), c->stream) != hipSuccess) {
         set_error("copying the feature table failed");
         return fail(BOOST_E_DEVICE);
@@ -211,9 +217,9 @@ int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels
 static int launch_round(boost_ctx* c, double* d_feature_err, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
     int rc;
     if (e0) VJB_HIP(hipEventRecord(e0, c->stream));
-    if ((rc = scan_launch(c->plan, c->jd, c->wgbest, (double2*)d_feature_err, c->stream)) != BOOST_OK) return rc;
+    if ((rc = scan_launch(c->plan, c->jd, (double2*)d_feature_err, c->stream)) != BOOST_OK) return rc;
     if (e1) VJB_HIP(hipEventRecord(e1, c->stream));
-    if ((rc = finalize_launch(c->jd, c->wgbest, c->plan.grid, c->stream)) != BOOST_OK) return rc;
+    if ((rc = update_launch(c->jd, c->plan.grid, c->stream)) != BOOST_OK) return rc;
     if (e2) VJB_HIP(hipEventRecord(e2, c->stream));
     c->launched++;
     return BOOST_OK;
@@ -283,8 +289,8 @@ int boost_round(boost_ctx* c, boost_stump* out_host, double* d_feature_err) {
 static int ensure_graph(boost_ctx* c) {
     if (c->gexec) return BOOST_OK;
     VJB_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    int rc = scan_launch(c->plan, c->jd, c->wgbest, nullptr, c->stream);
-    if (rc == BOOST_OK) rc = finalize_launch(c->jd, c->wgbest, c->plan.grid, c->stream);
+    int rc = scan_launch(c->plan, c->jd, nullptr, c->stream);
+    if (rc == BOOST_OK) rc = update_launch(c->jd, c->plan.grid, c->stream);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (rc != BOOST_OK) { if (g) hipGraphDestroy(g); return rc; }

@@ -15,6 +15,7 @@ constexpr int64_t kMaxN = 32767;        // 15-bit window indices in the sorted k
 constexpr int64_t kNarrowMaxN = 16383;  // 14-bit indices (+ dummy index n) in the narrow key format
 constexpr int kRing = 4096;             // device stump ring entries
 constexpr int kWave = 64;
+constexpr int kUpdWg = 256;             // windows per update workgroup
 
 // ---------------------------------------------------------------- feature descriptor
 // Packed uint32: type [0,3) | x [3,8) | y [8,13) | (cw-1) [13,18) | (ch-1) [18,23).
@@ -109,18 +110,24 @@ __host__ __device__ inline void decode_pair(int narrow, uint32_t d, uint32_t& i0
     else { i0 = (d & 0xFFFF) >> 1; f0 = d & 1; i1 = d >> 17; f1 = (d >> 16) & 1; }
 }
 
+// A dword of two padding keys (window index n: the zero table entry, no run end).
+__host__ __device__ inline uint32_t pad_dword(const KeyGeom& g) {
+    return encode_pair(g.narrow, (uint32_t)g.n, 0u, (uint32_t)g.n, 0u);
+}
+
 // ---------------------------------------------------------------- device state of one job
 // Lives in the workspace; written by the kernels, read by the host only on request.
 struct JobState {
-    double t_pos, t_neg;     // class totals of the scan's weight table
-    double wsum;             // sum of the weights before the last normalisation
+    double t_pos, t_neg;     // class totals of the last scan's weight table
+    double sum_w;            // S: the stored weights divided by S are the normalised weights of the round
     int32_t round;           // rounds completed
     int32_t stopped;         // STOP policy triggered
     int32_t n_pos;           // l
     int32_t label_error;     // a label other than 0/1 was seen
     int32_t weight_error;    // boost_set_weights saw a non-finite / negative / zero-sum input
-    int32_t launches;        // finalize launches (ring slot of the next record)
-    int32_t pad[2];
+    int32_t launches;        // scan launches (ring slot of the next record)
+    int32_t wpar;            // which half of the weight buffer holds the current weights
+    int32_t cur;             // wpar as seen by the last scan (read by the update kernel)
 };
 
 // Per-workgroup best stump candidate written by the scan kernel.
@@ -128,7 +135,7 @@ struct WgBest {
     double eps;
     int64_t feature;   // -1: none
     int32_t polarity;
-    int32_t pad;
+    int32_t lane;      // lane holding the extreme running sum (-1: the empty split k = 0)
 };
 
 // Everything a kernel needs to know about one job.
@@ -136,8 +143,11 @@ struct JobDev {
     const uint4* keys;         // F rows of row_units 16-byte units
     const int32_t* ii;         // [(H+1)(W+1)][ii_stride]
     const uint32_t* ftab;      // [F] packed descriptors
-    double* w;                 // [n] FP64 weights (internal order)
-    void* wtab;                // [n + 1] signed float or double weight table (+ zero at n)
+    double* w;                 // [2][n] FP64 weights (internal order), double buffered: half st->wpar is
+                               // current; normalised weights = w / sum(wpart)
+    double* wpart;             // [n_part] partial sums of w, summed in index order
+    WgBest* wgb;               // [scan grid] per-workgroup candidates
+    const uint4* pad;          // one unit of padding keys (window index n, no run end)
     JobState* st;
     boost_stump* ring;         // [kRing]
     const int32_t* perm;       // internal -> caller
@@ -147,8 +157,12 @@ struct JobDev {
     int64_t ii_stride;
     int32_t W, H;
     int32_t precision, on_perfect;
+    int32_t n_part;            // update workgroups (256 windows each)
+    int32_t unused;
     double eps_floor;
 };
+
+__device__ __forceinline__ double* weights(const JobDev& jd, int par) { return jd.w + (int64_t)par * jd.g.n; }
 
 // ---------------------------------------------------------------- host helpers
 void set_error(const std::string& msg);

@@ -110,15 +110,17 @@ int integral_launch(const JobDev& jd, const uint8_t* d_images, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- weights
-// Table 2 of Section 2.3: 1/(2l) for positives, 1/(2m) for negatives, then
-// the normalisation of step 1.
+// Table 2 of Section 2.3: 1/(2l) for positives, 1/(2m) for negatives.  The
+// stored weights divided by the sum of the partials are the normalised ones
+// (step 1); the scan normalises as it fills its table.
 __global__ __launch_bounds__(1024) void k_init_weights(JobDev jd) {
-    __shared__ double sh[16];
+    __shared__ double sh[4];
     const int64_t n = jd.g.n, l = jd.st->n_pos, m = n - l;
     const double wp = 1.0 / (2.0 * (double)l), wn = 1.0 / (2.0 * (double)m);
-    for (int64_t i = threadIdx.x; i < n; i += 1024) jd.w[i] = i < l ? wp : wn;
+    double* w = weights(jd, jd.st->wpar);
+    for (int64_t i = threadIdx.x; i < n; i += 1024) w[i] = i < l ? wp : wn;
     __syncthreads();
-    prep_weights<1024>(jd, sh);
+    reset_partials(jd, w, sh);
 }
 
 int init_weights_launch(const JobDev& jd, hipStream_t s) {
@@ -127,30 +129,31 @@ int init_weights_launch(const JobDev& jd, hipStream_t s) {
     return BOOST_OK;
 }
 
-// Caller weights -> validate -> internal order -> normalise and rebuild the table.
+// Caller weights -> validate -> internal order.  Rejected input leaves the
+// stored weights untouched.
 __global__ __launch_bounds__(1024) void k_set_weights(JobDev jd, const double* __restrict__ src, double* __restrict__ tmp) {
-    __shared__ double sh[16];
+    __shared__ double sh[4];
     __shared__ int s_bad;
     const int64_t n = jd.g.n;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
-    double part = 0.0;
     int bad = 0;
     for (int64_t e = threadIdx.x; e < n; e += 1024) {
         const double v = src[e];
         if (!(v >= 0.0) || !(v <= 1.0e308)) bad = 1;
         tmp[jd.inv[e]] = v;
-        part += v;
     }
     if (bad) atomicOr(&s_bad, 1);
-    const double sum = block_sum<1024>(part, sh);
+    __syncthreads();
+    const double sum = fixed_sum256(n, [&](int64_t i) { return tmp[i]; }, sh);
     if (s_bad || !(sum > 0.0) || !(sum <= 1.0e308)) {
         if (threadIdx.x == 0) jd.st->weight_error = 1;
         return;
     }
-    for (int64_t i = threadIdx.x; i < n; i += 1024) jd.w[i] = tmp[i];
+    double* w = weights(jd, jd.st->wpar);
+    for (int64_t i = threadIdx.x; i < n; i += 1024) w[i] = tmp[i];
     __syncthreads();
-    prep_weights<1024>(jd, sh);
+    reset_partials(jd, w, sh);
     if (threadIdx.x == 0) jd.st->weight_error = 0;
 }
 
@@ -160,15 +163,15 @@ int set_weights_launch(const JobDev& jd, const double* d_w, double* tmp, hipStre
     return BOOST_OK;
 }
 
-__global__ void k_get_weights(const double* __restrict__ w, const int32_t* __restrict__ perm, int64_t n,
-                              double* __restrict__ out) {
+__global__ void k_get_weights(JobDev jd, double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[perm[i]] = w[i];
+    const double rS = 1.0 / weight_sum(jd);   // whole wave
+    if (i < jd.g.n) out[jd.perm[i]] = weights(jd, jd.st->wpar)[i] * rS;
 }
 
 int get_weights_launch(const JobDev& jd, double* d_out, hipStream_t s) {
     const int64_t n = jd.g.n;
-    hipLaunchKernelGGL(k_get_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, jd.w, jd.perm, n, d_out);
+    hipLaunchKernelGGL(k_get_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, jd, d_out);
     VJB_HIP(hipGetLastError());
     return BOOST_OK;
 }

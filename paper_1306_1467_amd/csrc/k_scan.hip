@@ -1,9 +1,12 @@
-// Per-round kernels of one job: the weighted-error scan over every feature
-// (Section 2.3 step 2 / Section 3.3.2 step 3a, all features at once) with the
-// first level of the argmin, and the finalize kernel that takes the argmin
-// over workgroups (Section 3.3.2 step 4a), recovers the threshold, computes
-// beta and alpha and applies the weight update and normalisation
-// (Section 2.3 steps 1 and 4).
+// Per-round kernels of one job.
+//
+// k_scan: every feature's best stump under the current weights (Section 2.3
+// step 2 / Section 3.3.2 step 3a, all features at once) and the first level
+// of the argmin per workgroup.  Normalisation (step 1) happens as each
+// workgroup fills its LDS weight table.
+// k_update: the second level of the argmin, split rank, threshold, beta and
+// alpha (steps 3-4), and the weight update w_i <- w_i beta^(1 - e_i) with
+// per-workgroup partial sums for the next normalisation.
 #include <float.h>
 
 #include "launch.h"
@@ -12,11 +15,13 @@
 namespace vjb {
 
 // LDS image of the scan kernel: the weight table at LDS address 0, so the key
-// bits of a window are directly its table byte offset; then one record per wave.
+// bits of a window are directly its table byte offset; then per-wave records
+// and reduction scratch.
 template <typename Wt, int CAP, int NW>
 struct alignas(16) ScanLds {
     Wt tab[CAP];
     WgBest wb[NW];
+    double sh[8];
 };
 
 // Table capacity (entries, including the zero slot at n) per key format.
@@ -26,54 +31,67 @@ struct TabCap {
                                                                           : (NARROW ? 16384 : 20224);
 };
 
-// ---------------------------------------------------------------- scan kernel
-// Persistent: every workgroup copies the signed weight table into LDS once,
-// then each wave takes features j = wave_id, wave_id + total_waves, ...
-template <int PREC, bool NARROW, int WG, int UNROLL>
-__global__ __launch_bounds__(WG) void k_scan(JobDev jd, WgBest* __restrict__ out, double2* __restrict__ ferr) {
-    using Wt = typename ScanTypes<PREC>::W;
-    __shared__ ScanLds<Wt, TabCap<PREC, NARROW>::value, WG / 64> lds;
-    Wt* tab = lds.tab;
-    WgBest* wb = lds.wb;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (jd.st->stopped) {
-        if (tid == 0) out[blockIdx.x] = WgBest{DBL_MAX, -1, 0, 0};
-        return;
-    }
-    const int64_t ntab = jd.g.n + 1;
-    const Wt* src = (const Wt*)jd.wtab;
-    for (int64_t i = tid; i < ntab; i += WG) tab[i] = src[i];
-    __syncthreads();
-    const double tp = jd.st->t_pos, tn = jd.st->t_neg;
-    const int cnt = jd.g.q + (lane < jd.g.rem ? 1 : 0);
-    const int64_t total_waves = (int64_t)gridDim.x * (WG / 64);
-    double best = DBL_MAX;
-    int64_t bj = -1;
-    int bp = 0;
-    for (int64_t j = (int64_t)blockIdx.x * (WG / 64) + wv; j < jd.F; j += total_waves) {
-        double ep, en;
-        scan_feature<PREC, NARROW, UNROLL>(jd.keys + j * jd.g.row_units, lane, cnt, tab, tp, tn, ep, en);
-        if (ferr != nullptr && lane == 0) ferr[j] = make_double2(ep, en);
-        const double e = fmin(ep, en);
-        if (e < best) { best = e; bj = j; bp = ep <= en ? 1 : -1; }
-    }
-    if (lane == 0) wb[wv] = WgBest{best, bj, bp, 0};
-    __syncthreads();
-    if (tid == 0) {
-        WgBest b = wb[0];
-        for (int k = 1; k < WG / 64; ++k) {
-            const WgBest c = wb[k];
-            if (c.feature >= 0 && (b.feature < 0 || c.eps < b.eps || (c.eps == b.eps && c.feature < b.feature))) b = c;
-        }
-        out[blockIdx.x] = b;
-    }
-}
-
-// ---------------------------------------------------------------- finalize
 __device__ __forceinline__ bool better(const WgBest& c, const WgBest& b) {
     return c.feature >= 0 && (b.feature < 0 || c.eps < b.eps || (c.eps == b.eps && c.feature < b.feature));
 }
 
+// ---------------------------------------------------------------- scan kernel
+// Persistent: every workgroup fills its LDS weight table once, then each wave
+// takes features j = wave_id, wave_id + total_waves, ...  Each workgroup
+// leaves its best candidate (the first level of the argmin).
+template <int PREC, bool NARROW, int WG, int UNROLL, bool PIPE>
+__global__ __launch_bounds__(WG) void k_scan(JobDev jd, double2* __restrict__ ferr) {
+    using Wt = typename ScanTypes<PREC>::W;
+    __shared__ ScanLds<Wt, TabCap<PREC, NARROW>::value, WG / 64> lds;
+    Wt* tab = lds.tab;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    WgBest best{DBL_MAX, -1, 0, -1};
+    if (!jd.st->stopped) {
+        const int par = jd.st->wpar;
+        const double S = weight_sum(jd);
+        double tp, tn;
+        fill_table<Wt>(jd, weights(jd, par), tab, 1.0 / S, WG, lds.sh, tp, tn);
+        if (blockIdx.x == 0 && tid == 0) {
+            jd.st->sum_w = S; jd.st->t_pos = tp; jd.st->t_neg = tn; jd.st->cur = par;
+        }
+        const int cnt = jd.g.q + (lane < jd.g.rem ? 1 : 0);
+        const int nb = (jd.g.q + (jd.g.rem > 0 ? 1 : 0) + UNROLL - 1) / UNROLL;
+        const int64_t total_waves = (int64_t)gridDim.x * (WG / 64);
+        int64_t j = (int64_t)blockIdx.x * (WG / 64) + wv;
+        // batch 0 of the next feature is loaded before the current feature's
+        // wave-level epilogue, so loads stay in flight across features
+        uint4 u[UNROLL];
+        if (j < jd.F) load_batch<UNROLL>(u, jd.keys + j * jd.g.row_units + lane, 0, nb, cnt, jd.pad);
+        for (; j < jd.F; j += total_waves) {
+            const uint4* p = jd.keys + j * jd.g.row_units + lane;
+            LaneAcc<PREC> a;
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
+            for (int b = 1; b < nb; ++b) {
+                load_batch<UNROLL>(u, p, b, nb, cnt, jd.pad);
+#pragma unroll
+                for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
+            }
+            const int64_t jn = j + total_waves;
+            if (jn < jd.F) load_batch<UNROLL>(u, jd.keys + jn * jd.g.row_units + lane, 0, nb, cnt, jd.pad);
+            const FeatureScan fs = finish_feature<PREC>(a, lane, tp, tn);
+            if (ferr != nullptr && lane == 0) ferr[j] = make_double2(fs.e_pos, fs.e_neg);
+            const bool pos = fs.e_pos <= fs.e_neg;
+            const double e = pos ? fs.e_pos : fs.e_neg;
+            if (e < best.eps) { best = WgBest{e, j, pos ? 1 : -1, pos ? fs.lane_pos : fs.lane_neg}; }
+        }
+    }
+    if (lane == 0) lds.wb[wv] = best;
+    __syncthreads();
+    if (tid == 0) {
+        WgBest b = lds.wb[0];
+        for (int k = 1; k < WG / 64; ++k)
+            if (better(lds.wb[k], b)) b = lds.wb[k];
+        jd.wgb[blockIdx.x] = b;
+    }
+}
+
+// ---------------------------------------------------------------- update kernel
 // Window index (internal order) at rank r of feature j.
 __device__ inline int32_t index_at_rank(const JobDev& jd, int64_t j, int64_t r) {
     const int64_t mu = unit_to_mem(jd.g, r >> 3);
@@ -85,73 +103,47 @@ __device__ inline int32_t index_at_rank(const JobDev& jd, int64_t j, int64_t r) 
     return (int32_t)((e & 1) ? i1 : i0);
 }
 
-// Rescan of the winning feature by one wave, in exactly the arithmetic of
-// scan_feature, returning the smallest split k attaining the extreme D.
-template <int PREC, bool NARROW>
-__device__ int64_t best_split(const JobDev& jd, int64_t j, int pol, int lane) {
-    using Wt = typename ScanTypes<PREC>::W;
-    using A = typename ScanTypes<PREC>::A;
-    const Wt* tab = (const Wt*)jd.wtab;
-    LaneAcc<PREC> a;
-    const int cnt = jd.g.q + (lane < jd.g.rem ? 1 : 0);
-    const int64_t start = lane_start(jd.g, lane);
-    const uint4* row = jd.keys + j * jd.g.row_units;
-    // same candidate values as LaneAcc::cand (the extreme over a lane is
-    // order independent), with the first rank where it is reached
-    decltype(a.add(Wt(0))) ext = pol > 0 ? -4 : 4;
-    int64_t ext_rank = -1;
-    for (int r = 0; r < cnt; ++r) {
-        const uint4 u = row[(int64_t)r * 64 + lane];
-        const uint32_t dw[4] = {u.x, u.y, u.z, u.w};
-        for (int h = 0; h < 4; ++h) {
-            const uint32_t d = dw[h];
-            const Wt w0 = tab_lo<Wt, NARROW>(tab, d);
-            const Wt w1 = tab_hi<Wt, NARROW>(tab, d);
-            const auto v0 = a.add(w0);
-            if (flag_lo<NARROW>(d) && (pol > 0 ? v0 > ext : v0 < ext)) { ext = v0; ext_rank = 8 * (start + r) + 2 * h; }
-            const auto v1 = a.add(w1);
-            if (flag_hi<NARROW>(d) && (pol > 0 ? v1 > ext : v1 < ext)) { ext = v1; ext_rank = 8 * (start + r) + 2 * h + 1; }
-        }
-    }
-    const A base = wave_exclusive<A>((A)a.total(), lane);
-    A c = ext_rank >= 0 ? base + (A)ext : (pol > 0 ? (A)-8 : (A)8);
-    A m = c;
-#pragma unroll
-    for (int o = 32; o; o >>= 1) m = pol > 0 ? fmax(m, __shfl_xor(m, o)) : fmin(m, __shfl_xor(m, o));
-    // k = 0 wins ties with D = 0 (smaller split)
-    if (pol > 0 ? !(m > (A)0) : !(m < (A)0)) return 0;
-    const unsigned long long hit = __ballot(c == m && ext_rank >= 0);
-    const int first = __ffsll(hit) - 1;
-    const int64_t rk = __shfl(ext_rank, first);
-    return rk + 1;
+struct UpdLds {
+    WgBest wb[kUpdWg / 64];
+    double sh[kUpdWg / 64];
+    int64_t k;
+    int32_t theta;
+    int32_t pad;
+};
+
+// Broadcast of lane src's value (src uniform across the wave).
+__device__ __forceinline__ float bcast(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double bcast(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
 }
 
+// Every workgroup: the argmin over the scan's workgroup candidates (Section
+// 3.3.2 step 4a), the split rank -- the first run end where the winning
+// lane's running sum reaches its extreme, recomputed in exactly the scan's
+// arithmetic from that lane's keys and table values -- and the integer
+// threshold; then the update of its own 256 windows
+//     w_i <- (w_i / S) * beta   if x_i is classified correctly (e_i = 0),
+//     w_i <- (w_i / S)          otherwise            (Section 2.3 step 4),
+// into the other half of the weight buffer, and its partial sum for the next
+// normalisation.  All workgroups reach the same stump; workgroup 0 records it.
 template <int PREC, bool NARROW>
-__global__ __launch_bounds__(1024) void k_finalize(JobDev jd, const WgBest* __restrict__ wgb, int n_wg) {
-    constexpr int NT = 1024;
-    __shared__ double sh[NT / 64];
-    __shared__ WgBest red[NT / 64];
-    __shared__ int64_t s_k;
-    __shared__ int32_t s_theta;
-    __shared__ double s_beta;
-    __shared__ int32_t s_update;
+__global__ __launch_bounds__(kUpdWg) void k_update(JobDev jd, int n_wg) {
+    using Wt = typename ScanTypes<PREC>::W;
+    __shared__ UpdLds lds;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     JobState* st = jd.st;
-    const int32_t t_round = st->round;
-    const int32_t slot = st->launches % kRing;
-    if (st->stopped) {
-        if (tid == 0) {
-            boost_stump rec = {};
-            rec.feature = -1; rec.round = -1;
-            jd.ring[slot] = rec;
-            st->launches = st->launches + 1;
-        }
-        return;
-    }
-    // 1. argmin over the workgroups' candidates
-    WgBest b{DBL_MAX, -1, 0, 0};
-    for (int k = tid; k < n_wg; k += NT) {
-        const WgBest c = wgb[k];
+    // 1. argmin over the scan workgroups' candidates
+    WgBest b{DBL_MAX, -1, 0, -1};
+    for (int k = tid; k < n_wg; k += kUpdWg) {
+        const WgBest c = jd.wgb[k];
         if (better(c, b)) b = c;
     }
 #pragma unroll
@@ -160,98 +152,163 @@ __global__ __launch_bounds__(1024) void k_finalize(JobDev jd, const WgBest* __re
         c.eps = __shfl_xor(b.eps, o);
         c.feature = __shfl_xor(b.feature, o);
         c.polarity = __shfl_xor(b.polarity, o);
-        c.pad = 0;
+        c.lane = __shfl_xor(b.lane, o);
         if (better(c, b)) b = c;
     }
-    if (lane == 0) red[wv] = b;
+    if (lane == 0) lds.wb[wv] = b;
     __syncthreads();
-    b = red[0];
-    for (int k = 1; k < NT / 64; ++k)
-        if (better(red[k], b)) b = red[k];
-    const int64_t j = b.feature;
-    const int pol = b.polarity;
-    if (j < 0) {   // no finite candidate (cannot happen with validated weights)
-        if (tid == 0) {
+    b = lds.wb[0];
+    for (int k = 1; k < kUpdWg / 64; ++k)
+        if (better(lds.wb[k], b)) b = lds.wb[k];
+    const bool lead = blockIdx.x == 0 && tid == 0;
+    if (b.feature < 0) {   // stopped earlier (or no finite candidate): no round
+        if (lead) {
             boost_stump rec = {};
             rec.feature = -1; rec.round = -1;
-            jd.ring[slot] = rec;
+            jd.ring[st->launches % kRing] = rec;
             st->launches = st->launches + 1;
         }
         return;
     }
+    const int64_t n = jd.g.n, j = b.feature;
+    const int pol = b.polarity;
     const uint32_t desc = jd.ftab[j];
     const int wp1 = jd.W + 1;
-    const int64_t n = jd.g.n;
-    // 2. split rank and 3. threshold (integer, exact under p f < p theta)
+    const int64_t l = st->n_pos;
+    const double S = st->sum_w;
+    const double rS = 1.0 / S;
+    const int par = st->cur;   // the scan's weights; this kernel writes the other half
+    const double* w_in = weights(jd, par);
+    double* w_out = weights(jd, par ^ 1);
+    // this workgroup's windows: values are loaded while the split is found
+    const int64_t i = (int64_t)blockIdx.x * kUpdWg + tid;
+    const int32_t f = i < n ? haar_value(jd.ii, jd.ii_stride, wp1, desc, i) : 0;
+    // 2. split rank and 3. threshold, by wave 0: lane r holds unit r of the
+    // winning lane's segment (window indices, table values, run-end flags);
+    // the running sum is then replayed in rank order with broadcasts.
     if (wv == 0) {
-        const int64_t k = best_split<PREC, NARROW>(jd, j, pol, lane);
-        if (lane == 0) {
-            int32_t theta;
-            if (pol > 0) {
-                theta = k < n ? haar_value(jd.ii, jd.ii_stride, wp1, desc, index_at_rank(jd, j, k))
-                              : haar_value(jd.ii, jd.ii_stride, wp1, desc, index_at_rank(jd, j, n - 1)) + 1;
-            } else {
-                theta = k > 0 ? haar_value(jd.ii, jd.ii_stride, wp1, desc, index_at_rank(jd, j, k - 1))
-                              : haar_value(jd.ii, jd.ii_stride, wp1, desc, index_at_rank(jd, j, 0)) - 1;
+        const int L = b.lane;
+        const int cntL = L >= 0 ? jd.g.q + (L < jd.g.rem ? 1 : 0) : 0;
+        const int64_t seg0 = L >= 0 ? 8 * lane_start(jd.g, L) : 0;
+        uint32_t idx[8];
+        Wt val[8];
+        uint32_t fb = 0;
+        if (lane < cntL) {
+            const uint4 u = jd.keys[j * jd.g.row_units + (int64_t)lane * 64 + L];
+            const uint32_t dw[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                uint32_t f0, f1;
+                decode_pair(jd.g.narrow, dw[h], idx[2 * h], f0, idx[2 * h + 1], f1);
+                fb |= (f0 << (2 * h)) | (f1 << (2 * h + 1));
             }
-            s_k = k;
-            s_theta = theta;
-            // 4. beta and alpha (FP64); eps = 0 is clamped to the floor
-            const double eps = b.eps;
-            const double epsc = eps > jd.eps_floor ? eps : jd.eps_floor;
-            const double beta = epsc / (1.0 - epsc);
-            s_beta = beta;
-            const bool stop = jd.on_perfect == BOOST_ON_PERFECT_STOP && !(eps > jd.eps_floor);
-            s_update = stop ? 0 : 1;
-            int t, x, y, cw, ch;
-            unpack_feature(desc, t, x, y, cw, ch);
-            boost_stump rec;
-            rec.feature = j; rec.type = t; rec.x = x; rec.y = y; rec.cell_w = cw; rec.cell_h = ch;
-            rec.polarity = pol; rec.threshold = theta; rec.split_rank = (int32_t)k; rec.round = t_round;
-            rec.pad = 0;
-            rec.error_raw = eps; rec.error = epsc; rec.beta = beta; rec.alpha = log(1.0 / beta);
-            jd.ring[slot] = rec;
-            if (stop) st->stopped = 1;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                val[e] = idx[e] < (uint32_t)n ? table_value<Wt>(w_in[idx[e]], rS, idx[e] < (uint32_t)l) : (Wt)0;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) { idx[e] = 0; val[e] = (Wt)0; }
+        }
+        int64_t k = 0;
+        if (L >= 0) {
+            LaneAcc<PREC> a;
+            decltype(a.add(Wt(0))) ext = pol > 0 ? -4 : 4;
+            int ext_rank = -1;
+            for (int r = 0; r < cntL; ++r) {
+                const uint32_t fr = bcast(fb, r);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const auto v = a.add(bcast(val[e], r));
+                    if (((fr >> e) & 1u) && (pol > 0 ? v > ext : v < ext)) { ext = v; ext_rank = 8 * r + e; }
+                }
+            }
+            k = seg0 + ext_rank + 1;
+        }
+        // window at the rank just above (p = +1) or at (p = -1) the split
+        const int64_t rk = pol > 0 ? (k < n ? k : n - 1) : (k > 0 ? k - 1 : 0);
+        int32_t wi;
+        if (L >= 0 && rk >= seg0 && rk < seg0 + 8 * cntL) {
+            const int r = (int)((rk - seg0) >> 3), e = (int)((rk - seg0) & 7);
+            uint32_t pick = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) pick = q == e ? idx[q] : pick;
+            wi = (int32_t)bcast(pick, r);
+        } else {
+            wi = index_at_rank(jd, j, rk);
+        }
+        if (lane == 0) {
+            const int32_t v = haar_value(jd.ii, jd.ii_stride, wp1, desc, wi);
+            lds.k = k;
+            lds.theta = pol > 0 ? (k < n ? v : v + 1) : (k > 0 ? v : v - 1);
         }
     }
     __syncthreads();
-    if (!s_update) {
-        if (tid == 0) { st->round = t_round + 1; st->launches = st->launches + 1; }
-        return;
+    // 4. beta, alpha (FP64); eps = 0 is clamped to the floor
+    const double eps = b.eps;
+    const double epsc = eps > jd.eps_floor ? eps : jd.eps_floor;
+    const double beta = epsc / (1.0 - epsc);
+    const bool stop = jd.on_perfect == BOOST_ON_PERFECT_STOP && !(eps > jd.eps_floor);
+    const int32_t theta = lds.theta;
+    if (lead) {
+        int t, x, y, cw, ch;
+        unpack_feature(desc, t, x, y, cw, ch);
+        boost_stump rec;
+        rec.feature = j; rec.type = t; rec.x = x; rec.y = y; rec.cell_w = cw; rec.cell_h = ch;
+        rec.polarity = pol; rec.threshold = theta; rec.split_rank = (int32_t)lds.k; rec.round = st->round;
+        rec.pad = 0;
+        rec.error_raw = eps; rec.error = epsc; rec.beta = beta; rec.alpha = log(1.0 / beta);
+        jd.ring[st->launches % kRing] = rec;
+        if (stop) st->stopped = 1;
+        else st->wpar = par ^ 1;
+        st->round = st->round + 1;
+        st->launches = st->launches + 1;
     }
-    // 5. update: w_i <- w_i * beta when x_i is classified correctly (e_i = 0)
-    const int32_t theta = s_theta;
-    const double beta = s_beta;
-    const int64_t l = st->n_pos;
-    for (int64_t i = tid; i < n; i += NT) {
-        const int32_t f = haar_value(jd.ii, jd.ii_stride, wp1, desc, i);
+    if (stop) return;   // weights unchanged
+    // 5. update and partial sum
+    double wn = 0.0;
+    if (i < n) {
         const int h = (int64_t)pol * f < (int64_t)pol * theta ? 1 : 0;
         const int y = i < l ? 1 : 0;
-        if (h == y) jd.w[i] = jd.w[i] * beta;
+        wn = w_in[i] * rS;
+        if (h == y) wn = wn * beta;
+        w_out[i] = wn;
     }
+#pragma unroll
+    for (int o = 32; o; o >>= 1) wn += __shfl_xor(wn, o);
+    if (lane == 0) lds.sh[wv] = wn;
     __syncthreads();
-    // 6. normalisation and the next round's table
-    prep_weights<NT>(jd, sh);
-    if (tid == 0) { st->round = t_round + 1; st->launches = st->launches + 1; }
+    if (tid == 0) {
+        double s = 0.0;
+        for (int k = 0; k < kUpdWg / 64; ++k) s += lds.sh[k];
+        jd.wpart[blockIdx.x] = s;
+    }
 }
 
 // ---------------------------------------------------------------- launchers
+// Launch schedules (workgroup size, units per batch, pipelined loads).
+struct Schedule { int wg, unroll, pipe; };
+static const Schedule kSchedules[] = {
+    {512, 10, 0}, {512, 8, 0}, {512, 6, 0}, {512, 15, 0}, {512, 4, 0}, {1024, 10, 0}, {512, 5, 0}, {256, 10, 0},
+};
+constexpr int kNumSchedules = (int)(sizeof(kSchedules) / sizeof(kSchedules[0]));
+
 template <int PREC, bool NARROW>
 static const void* scan_kernel_ptr(int schedule) {
     switch (schedule) {
-    case 1: return (const void*)k_scan<PREC, NARROW, 1024, 4>;
-    case 2: return (const void*)k_scan<PREC, NARROW, 256, 4>;
-    case 3: return (const void*)k_scan<PREC, NARROW, 512, 8>;
-    case 4: return (const void*)k_scan<PREC, NARROW, 1024, 8>;
-    case 5: return (const void*)k_scan<PREC, NARROW, 512, 2>;
-    default: return (const void*)k_scan<PREC, NARROW, 512, 4>;
+    case 1: return (const void*)k_scan<PREC, NARROW, 512, 8, false>;
+    case 2: return (const void*)k_scan<PREC, NARROW, 512, 6, false>;
+    case 3: return (const void*)k_scan<PREC, NARROW, 512, 15, false>;
+    case 4: return (const void*)k_scan<PREC, NARROW, 512, 4, false>;
+    case 5: return (const void*)k_scan<PREC, NARROW, 1024, 10, false>;
+    case 6: return (const void*)k_scan<PREC, NARROW, 512, 5, false>;
+    case 7: return (const void*)k_scan<PREC, NARROW, 256, 10, false>;
+    default: return (const void*)k_scan<PREC, NARROW, 512, 10, false>;
     }
 }
 
-int scan_schedule_count() { return 6; }
+int scan_schedule_count() { return kNumSchedules; }
 int scan_schedule_wg(int schedule) {
-    static const int wg[6] = {512, 1024, 256, 512, 1024, 512};
-    return wg[(schedule >= 0 && schedule < 6) ? schedule : 0];
+    return kSchedules[(schedule >= 0 && schedule < kNumSchedules) ? schedule : 0].wg;
 }
 
 const void* scan_kernel(int precision, bool narrow, int schedule) {
@@ -279,35 +336,35 @@ int scan_plan(ScanPlan& p, int precision, bool narrow, int schedule, int64_t n, 
     int per_cu = 0;
     VJB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p.kernel, p.wg, p.lds));
     if (per_cu < 1) {
-        set_error("scan kernel does not fit on a compute unit (weight table too large)");
+        set_error("scan kernel does not fit on a compute unit");
         return BOOST_E_INVALID;
     }
     int64_t grid = (int64_t)per_cu * num_cu;
-    const int64_t waves_needed = F;  // one feature per wave at least
-    const int64_t max_grid = (waves_needed + p.wg / 64 - 1) / (p.wg / 64);
+    const int64_t max_grid = (F + p.wg / 64 - 1) / (p.wg / 64);   // at least one feature per wave
     if (grid > max_grid) grid = max_grid;
     if (grid > kMaxScanGrid) grid = kMaxScanGrid;
     p.grid = (int)grid;
     return BOOST_OK;
 }
 
-int scan_launch(const ScanPlan& p, const JobDev& jd, WgBest* out, double2* ferr, hipStream_t s) {
-    void* args[] = {(void*)&jd, (void*)&out, (void*)&ferr};
+int scan_launch(const ScanPlan& p, const JobDev& jd, double2* ferr, hipStream_t s) {
+    void* args[] = {(void*)&jd, (void*)&ferr};
     VJB_HIP(hipLaunchKernel(p.kernel, dim3(p.grid), dim3(p.wg), args, p.lds, s));
     return BOOST_OK;
 }
 
-int finalize_launch(const JobDev& jd, const WgBest* wgb, int n_wg, hipStream_t s) {
+int update_launch(const JobDev& jd, int n_wg, hipStream_t s) {
     const bool narrow = jd.g.narrow != 0;
     const void* k;
     switch (jd.precision) {
-    case BOOST_PREC_FP32: k = narrow ? (const void*)k_finalize<BOOST_PREC_FP32, true> : (const void*)k_finalize<BOOST_PREC_FP32, false>; break;
-    case BOOST_PREC_FP32_KAHAN: k = narrow ? (const void*)k_finalize<BOOST_PREC_FP32_KAHAN, true> : (const void*)k_finalize<BOOST_PREC_FP32_KAHAN, false>; break;
-    case BOOST_PREC_FP64: k = narrow ? (const void*)k_finalize<BOOST_PREC_FP64, true> : (const void*)k_finalize<BOOST_PREC_FP64, false>; break;
-    default: k = narrow ? (const void*)k_finalize<BOOST_PREC_FP32_WIDE, true> : (const void*)k_finalize<BOOST_PREC_FP32_WIDE, false>; break;
+    case BOOST_PREC_FP32: k = narrow ? (const void*)k_update<BOOST_PREC_FP32, true> : (const void*)k_update<BOOST_PREC_FP32, false>; break;
+    case BOOST_PREC_FP32_KAHAN: k = narrow ? (const void*)k_update<BOOST_PREC_FP32_KAHAN, true> : (const void*)k_update<BOOST_PREC_FP32_KAHAN, false>; break;
+    case BOOST_PREC_FP64: k = narrow ? (const void*)k_update<BOOST_PREC_FP64, true> : (const void*)k_update<BOOST_PREC_FP64, false>; break;
+    default: k = narrow ? (const void*)k_update<BOOST_PREC_FP32_WIDE, true> : (const void*)k_update<BOOST_PREC_FP32_WIDE, false>; break;
     }
-    void* args[] = {(void*)&jd, (void*)&wgb, (void*)&n_wg};
-    VJB_HIP(hipLaunchKernel(k, dim3(1), dim3(1024), args, 0, s));
+    JobDev a = jd;
+    void* args[] = {(void*)&a, (void*)&n_wg};
+    VJB_HIP(hipLaunchKernel(k, dim3((unsigned)jd.n_part), dim3(kUpdWg), args, 0, s));
     return BOOST_OK;
 }
 

@@ -7,6 +7,8 @@ namespace vjb {
 
 constexpr int kMaxScanGrid = 8192;   // upper bound of scan workgroups (per-workgroup records)
 constexpr int kMaxSortGrid = 1024;   // upper bound of sort workgroups (fallback scratch)
+constexpr int kMaxPart = (int)((kMaxN + kUpdWg - 1) / kUpdWg);   // update workgroups of the largest job (<= 128)
+static_assert(kMaxPart <= 128, "weight_sum reads at most 128 partials");
 
 struct ScanPlan {
     const void* kernel = nullptr;
@@ -20,8 +22,8 @@ int scan_schedule_count();
 int scan_schedule_wg(int schedule);
 int64_t scan_table_capacity(int precision, bool narrow);
 int scan_plan(ScanPlan& p, int precision, bool narrow, int schedule, int64_t n, int64_t F, int num_cu);
-int scan_launch(const ScanPlan& p, const JobDev& jd, WgBest* out, double2* ferr, hipStream_t s);
-int finalize_launch(const JobDev& jd, const WgBest* wgb, int n_wg, hipStream_t s);
+int scan_launch(const ScanPlan& p, const JobDev& jd, double2* ferr, hipStream_t s);
+int update_launch(const JobDev& jd, int n_wg, hipStream_t s);
 
 // k_prep.hip
 int ingest_launch(const JobDev& jd, const uint8_t* d_labels, int64_t n, hipStream_t s);

@@ -164,108 +164,179 @@ __device__ __forceinline__ uint4 ld_stream(const uint4* p) {
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
-// Exclusive wave prefix of the lane totals (fixed order: Hillis-Steele).
-template <typename A>
-__device__ __forceinline__ A wave_exclusive(A tot, int lane) {
-    A incl = tot;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const A y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
-    }
-    A ex = __shfl_up(incl, 1);
-    return lane == 0 ? (A)0 : ex;
+// ---------------------------------------------------------------- cross-lane (DPP)
+// Value of another lane selected by a DPP control (CDNA wave64 encodings:
+// 0x111.. row_shr:k, 0x138 wave_shr:1, 0x140 row_mirror, 0x141
+// row_half_mirror, 0x142 row_bcast:15, 0x143 row_bcast:31, 0x00-0xFF
+// quad_perm); lanes that receive nothing keep `old`.
+template <int CTRL, int RM, int BM, bool BC>
+__device__ __forceinline__ double dpp(double v, double old) {
+    const long long b = __double_as_longlong(v), o = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)b, CTRL, RM, BM, BC);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, RM, BM, BC);
+    return __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
+}
+template <int CTRL, int RM, int BM, bool BC>
+__device__ __forceinline__ float dpp(float v, float old) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, RM, BM, BC));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ float read_lane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// One wave scans one feature's row; returns (e+, e-) in every lane.
-// row points at the feature's first unit; cnt = units of this lane.
-template <int PREC, bool NARROW, int UNROLL>
-__device__ __forceinline__ void scan_feature(const uint4* __restrict__ row, int lane, int cnt,
-                                             const typename ScanTypes<PREC>::W* tab, double t_pos,
-                                             double t_neg, double& e_pos, double& e_neg) {
+// Exclusive prefix of the lane totals across the wave, in a fixed order:
+// inclusive scan within rows of 16 (shifts 1, 2, 4, 8), then row 0's total
+// into row 1 and row 2's into row 3, then rows 0-1's total into rows 2-3;
+// finally a shift by one lane.
+template <typename A>
+__device__ __forceinline__ A wave_exclusive(A tot) {
+    A v = tot;
+    v += dpp<0x111, 0xF, 0xF, true>(v, (A)0);
+    v += dpp<0x112, 0xF, 0xF, true>(v, (A)0);
+    v += dpp<0x114, 0xF, 0xF, true>(v, (A)0);
+    v += dpp<0x118, 0xF, 0xF, true>(v, (A)0);
+    v += dpp<0x142, 0xA, 0xF, false>(v, (A)0);
+    v += dpp<0x143, 0xC, 0xF, false>(v, (A)0);
+    return dpp<0x138, 0xF, 0xF, true>(v, (A)0);
+}
+
+// Wave-wide maximum (MAX) or minimum, the same value in every lane.
+template <bool MAX, typename A>
+__device__ __forceinline__ A wave_extreme(A v) {
+    auto op = [](A a, A b) { return MAX ? fmax(a, b) : fmin(a, b); };
+    v = op(v, dpp<0xB1, 0xF, 0xF, false>(v, v));    // quad_perm [1,0,3,2]
+    v = op(v, dpp<0x4E, 0xF, 0xF, false>(v, v));    // quad_perm [2,3,0,1]
+    v = op(v, dpp<0x141, 0xF, 0xF, false>(v, v));   // row_half_mirror
+    v = op(v, dpp<0x140, 0xF, 0xF, false>(v, v));   // row_mirror
+    v = op(v, dpp<0x142, 0xA, 0xF, false>(v, v));   // row_bcast:15
+    v = op(v, dpp<0x143, 0xC, 0xF, false>(v, v));   // row_bcast:31
+    return read_lane(v, 63);
+}
+
+// Result of one feature's scan, identical in every lane of the wave.
+struct FeatureScan {
+    double e_pos, e_neg;   // best error for p = +1 / p = -1
+    int lane_pos, lane_neg;  // first lane holding the extreme (-1: the empty split k = 0)
+};
+
+// Loads batch b (UNROLL units) of one lane's segment.  All batches but the
+// last (nb - 1) are full for every lane; in the last one, units past the
+// lane's segment come from `pad` (a unit of padding keys, cache resident), so
+// the loads need no branches.
+template <int UNROLL>
+__device__ __forceinline__ void load_batch(uint4* u, const uint4* __restrict__ p, int b, int nb, int cnt,
+                                           const uint4* __restrict__ pad) {
+    if (b + 1 < nb) {
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) u[k] = ld_stream(p + 64 * (b * UNROLL + k));
+    } else {
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) {
+            const int r = b * UNROLL + k;
+            u[k] = ld_stream(r < cnt ? p + 64 * r : pad);
+        }
+    }
+}
+
+// Wave-level end of one feature's scan: lane totals -> exclusive prefix ->
+// global extremes of the running sum at run ends -> errors for both polarities.
+template <int PREC>
+__device__ __forceinline__ FeatureScan finish_feature(const LaneAcc<PREC>& a, int lane, double t_pos, double t_neg) {
     using A = typename ScanTypes<PREC>::A;
-    LaneAcc<PREC> a;
-    const uint4* p = row + lane;
-    int r = 0;
-    for (; r + UNROLL <= cnt; r += UNROLL) {
-        uint4 u[UNROLL];
-#pragma unroll
-        for (int k = 0; k < UNROLL; ++k) u[k] = ld_stream(p + 64 * k);
-        p += 64 * UNROLL;
-#pragma unroll
-        for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
-    }
-    for (; r < cnt; ++r) {
-        const uint4 u = ld_stream(p);
-        p += 64;
-        scan_unit<PREC, NARROW>(a, tab, u);
-    }
-    const A base = wave_exclusive<A>((A)a.total(), lane);
-    A cmx = base + (A)a.vmax();
-    A cmn = base + (A)a.vmin();
-#pragma unroll
-    for (int o = 32; o; o >>= 1) {
-        cmx = fmax(cmx, __shfl_xor(cmx, o));
-        cmn = fmin(cmn, __shfl_xor(cmn, o));
-    }
-    // k = 0 (nothing below the threshold) is always realisable: D_0 = 0.
+    const A base = wave_exclusive<A>((A)a.total());
+    const A lmx = base + (A)a.vmax();
+    const A lmn = base + (A)a.vmin();
+    A cmx = wave_extreme<true>(lmx);
+    A cmn = wave_extreme<false>(lmn);
+    FeatureScan r;
+    // k = 0 (nothing below the threshold) is always realisable: D_0 = 0, and
+    // it is the smallest split, so it wins ties.
+    r.lane_pos = cmx > (A)0 ? __ffsll(__ballot(lmx == cmx)) - 1 : -1;
+    r.lane_neg = cmn < (A)0 ? __ffsll(__ballot(lmn == cmn)) - 1 : -1;
     cmx = fmax(cmx, (A)0);
     cmn = fmin(cmn, (A)0);
-    e_pos = (double)((A)t_pos - cmx);
-    e_neg = (double)((A)t_neg + cmn);
+    r.e_pos = (double)((A)t_pos - cmx);
+    r.e_neg = (double)((A)t_neg + cmn);
+    return r;
 }
 
-// ---------------------------------------------------------------- block reductions
-// Deterministic for a fixed block size: per-thread partials in a fixed
-// stride pattern, a fixed butterfly per wave, then wave partials in order.
-template <int NT>
-__device__ __forceinline__ double block_sum(double v, double* sh) {
+// ---------------------------------------------------------------- block sums
+// Sum of v(i), i in [0, n), in an order that does not depend on the block
+// size (>= 256 threads): thread t < 256 adds v(t), v(t + 256), ... in turn;
+// lane 0 of each of the four waves takes a fixed butterfly; the four wave sums
+// are added in order.  Every thread returns the same value.  sh: 4 doubles.
+template <typename Fn>
+__device__ __forceinline__ double fixed_sum256(int64_t n, Fn v, double* sh) {
+    double p = 0.0;
+    if (threadIdx.x < 256)
+        for (int64_t i = threadIdx.x; i < n; i += 256) p += v(i);
 #pragma unroll
-    for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 32; o; o >>= 1) p += __shfl_xor(p, o);
     __syncthreads();
-    if (lane == 0) sh[wv] = v;
+    if (threadIdx.x < 256 && (threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = p;
     __syncthreads();
-    double s = 0.0;
-    for (int k = 0; k < NT / 64; ++k) s += sh[k];
+    const double s = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    __syncthreads();
     return s;
 }
 
-// Weight preparation (Section 2.3 step 1, normalisation): w <- w / sum w, the
-// scan's signed table w^ (rounded to the table type) with a zero entry at n
-// for padding keys, and the class totals T+ / T- of that table.
-// Windows are in internal order, positives (i < l) first.
-template <int NT>
-__device__ void prep_weights(const JobDev& jd, double* sh) {
+// S = sum of the stored weights from the update workgroups' partial sums, in
+// a fixed order (lane k adds partials k and k + 64; a fixed butterfly; lane
+// 0's value).  Needs a whole wave; every lane returns the same value.
+__device__ __forceinline__ double weight_sum(const JobDev& jd) {
+    const int lane = threadIdx.x & 63;
+    double p = lane < jd.n_part ? jd.wpart[lane] : 0.0;
+    if (lane + 64 < jd.n_part) p += jd.wpart[lane + 64];
+#pragma unroll
+    for (int o = 32; o; o >>= 1) p += __shfl_xor(p, o);
+    return __shfl(p, 0);
+}
+
+// One entry of the scan's signed weight table: the normalised weight
+// w_i * (1 / S) rounded to the table type, negated for negatives.
+template <typename Wt>
+__device__ __forceinline__ Wt table_value(double w, double rS, bool positive) {
+    const Wt wn = (Wt)(w * rS);
+    return positive ? wn : -wn;
+}
+
+// Section 2.3 step 1, normalisation, fused into the scan's table fill: the
+// signed table, a zero entry at n for padding keys, and the class totals T+ /
+// T- of the table (one fixed-order pass: thread t < 256 adds entries t, t +
+// 256, ... into T+ or T-, then a fixed butterfly per wave and the four wave
+// sums in order).  Every workgroup computes the same values.
+template <typename Wt>
+__device__ __forceinline__ void fill_table(const JobDev& jd, const double* w, Wt* tab, double rS, int nt, double* sh,
+                                           double& tp, double& tn) {
     const int64_t n = jd.g.n;
     const int64_t l = jd.st->n_pos;
-    double part = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += NT) part += jd.w[i];
-    const double sum = block_sum<NT>(part, sh);
-    const bool fp64 = jd.precision == BOOST_PREC_FP64;
-    double tp = 0.0, tn = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += NT) {
-        const double wn = jd.w[i] / sum;
-        jd.w[i] = wn;
-        if (fp64) {
-            ((double*)jd.wtab)[i] = i < l ? wn : -wn;
-            if (i < l) tp += wn; else tn += wn;
-        } else {
-            const float wf = (float)wn;
-            ((float*)jd.wtab)[i] = i < l ? wf : -wf;
-            if (i < l) tp += (double)wf; else tn += (double)wf;
+    for (int64_t i = threadIdx.x; i < n; i += nt) tab[i] = table_value<Wt>(w[i], rS, i < l);
+    if (threadIdx.x == 0) tab[n] = (Wt)0;
+    __syncthreads();
+    double p = 0.0, q = 0.0;
+    if (threadIdx.x < 256)
+        for (int64_t i = threadIdx.x; i < n; i += 256) {
+            const double v = (double)tab[i];
+            if (i < l) p += v; else q -= v;
         }
-    }
-    if (threadIdx.x == 0) {
-        if (fp64) ((double*)jd.wtab)[n] = 0.0; else ((float*)jd.wtab)[n] = 0.f;
-    }
-    tp = block_sum<NT>(tp, sh);
-    tn = block_sum<NT>(tn, sh);
-    if (threadIdx.x == 0) {
-        jd.st->t_pos = tp;
-        jd.st->t_neg = tn;
-        jd.st->wsum = sum;
-    }
+#pragma unroll
+    for (int o = 32; o; o >>= 1) { p += __shfl_xor(p, o); q += __shfl_xor(q, o); }
+    if (threadIdx.x < 256 && (threadIdx.x & 63) == 0) { sh[threadIdx.x >> 6] = p; sh[4 + (threadIdx.x >> 6)] = q; }
+    __syncthreads();
+    tp = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    tn = ((sh[4] + sh[5]) + sh[6]) + sh[7];
+}
+
+// Stored weights w and their partial sums for a fresh weight vector: one
+// partial holding the whole (fixed-order) sum, the rest zero.
+__device__ __forceinline__ void reset_partials(const JobDev& jd, const double* w, double* sh) {
+    const double s = fixed_sum256(jd.g.n, [&](int64_t i) { return w[i]; }, sh);
+    for (int k = threadIdx.x; k < jd.n_part; k += blockDim.x) jd.wpart[k] = k == 0 ? s : 0.0;
 }
 
 }  // namespace vjb
