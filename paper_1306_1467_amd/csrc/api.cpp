@@ -36,7 +36,7 @@ struct Layout {
 static bool make_layout(int64_t n, const boost_feature_set* fs, Layout& L) {
     const int64_t F = host_feature_count(fs);
     if (F <= 0) return false;
-    const KeyGeom g = make_geom(n);
+    const KeyGeom g = make_geom(n, 64);
     const int64_t P = (int64_t)(fs->window_w + 1) * (fs->window_h + 1);
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off += a256(bytes); return o; };
@@ -174,7 +174,7 @@ int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels
     jd.ring = (boost_stump*)(ws + L.ring);
     jd.perm = (const int32_t*)(ws + L.perm);
     jd.inv = (const int32_t*)(ws + L.inv);
-    jd.g = make_geom(n);
+    jd.g = make_geom(n, scan_schedule_lanes(o->schedule_id));
     jd.F = c->F;
     jd.ii_stride = ii_stride_of(n);
     jd.W = fs->window_w;

@@ -63,18 +63,20 @@ __device__ __forceinline__ int32_t haar_value(const int32_t* __restrict__ ii, in
 
 // ---------------------------------------------------------------- sorted-key layout
 // Per feature, the n windows in ascending value order are split into 8-key
-// units (16 bytes).  The Nc = ceil(n/8) units are dealt to the 64 lanes of a
-// wave as contiguous segments: lane L owns q+1 units if L < rem, else q
-// (q = Nc / 64, rem = Nc % 64), starting at unit start(L) = L*q + min(L, rem).
-// In memory, the r-th unit of every lane's segment sits together:
-// memory unit r*64 + L.  A wave then reads 1 KiB contiguous per step while
-// each lane walks its own contiguous run of ranks.
+// units (16 bytes).  The Nc = ceil(n/8) units are dealt to the `lanes` lanes
+// (16, 32 or 64) that scan the feature as contiguous segments: lane L owns
+// q+1 units if L < rem, else q (q = Nc / lanes, rem = Nc % lanes), starting
+// at unit start(L) = L*q + min(L, rem).  In memory, the r-th unit of every
+// lane's segment sits together: memory unit r*lanes + L.  The lanes of a
+// feature then read lanes*16 contiguous bytes per step while each walks its
+// own contiguous run of ranks.
 struct KeyGeom {
     int64_t n;        // windows
     int64_t nc;       // units of 8 keys
     int32_t q, rem;   // units per lane (q or q+1)
     int64_t row_units;// units between consecutive features (row stride / 16 B)
-    int narrow;       // 1: 14-bit indices (n <= 16383), 0: 15-bit
+    int32_t narrow;   // 1: 14-bit indices (n <= 16383), 0: 15-bit
+    int32_t lanes;    // lanes per feature
 };
 
 __host__ __device__ inline int64_t lane_start(const KeyGeom& g, int L) {
@@ -86,12 +88,12 @@ __host__ __device__ inline int64_t unit_to_mem(const KeyGeom& g, int64_t u) {
     int64_t L, r;
     if (u < big) { L = u / (g.q + 1); r = u % (g.q + 1); }
     else { const int64_t v = u - big; L = g.rem + v / g.q; r = v % g.q; }
-    return r * 64 + L;
+    return r * g.lanes + L;
 }
 // memory unit -> rank-order unit
 __host__ __device__ inline int64_t mem_to_unit(const KeyGeom& g, int64_t mu) {
-    const int64_t r = mu >> 6;
-    const int L = (int)(mu & 63);
+    const int64_t r = mu / g.lanes;
+    const int L = (int)(mu % g.lanes);
     return lane_start(g, L) + r;
 }
 
@@ -184,7 +186,7 @@ bool valid_options(const boost_options* o);
 int host_feature_desc(const boost_feature_set* fs, int64_t j, boost_feature* out);
 void host_feature_table(const boost_feature_set* fs, uint32_t* out);
 
-KeyGeom make_geom(int64_t n);
+KeyGeom make_geom(int64_t n, int lanes);
 int64_t ii_stride_of(int64_t n);
 
 }  // namespace vjb

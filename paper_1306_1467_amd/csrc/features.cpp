@@ -71,14 +71,15 @@ void host_feature_table(const boost_feature_set* fs, uint32_t* out) {
     }
 }
 
-KeyGeom make_geom(int64_t n) {
+KeyGeom make_geom(int64_t n, int lanes) {
     KeyGeom g;
     g.n = n;
     g.nc = (n + 7) / 8;
-    g.q = (int32_t)(g.nc / 64);
-    g.rem = (int32_t)(g.nc % 64);
+    g.q = (int32_t)(g.nc / lanes);
+    g.rem = (int32_t)(g.nc % lanes);
     g.row_units = (g.nc + 15) / 16 * 16;   // 256-byte aligned rows
     g.narrow = n <= kNarrowMaxN ? 1 : 0;
+    g.lanes = lanes;
     return g;
 }
 

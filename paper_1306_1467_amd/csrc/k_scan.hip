@@ -15,12 +15,12 @@
 namespace vjb {
 
 // LDS image of the scan kernel: the weight table at LDS address 0, so the key
-// bits of a window are directly its table byte offset; then per-wave records
-// and reduction scratch.
-template <typename Wt, int CAP, int NW>
+// bits of a window are directly its table byte offset; then per-group
+// records and reduction scratch.
+template <typename Wt, int CAP, int NG>
 struct alignas(16) ScanLds {
     Wt tab[CAP];
-    WgBest wb[NW];
+    WgBest wb[NG];
     double sh[8];
 };
 
@@ -35,60 +35,104 @@ __device__ __forceinline__ bool better(const WgBest& c, const WgBest& b) {
     return c.feature >= 0 && (b.feature < 0 || c.eps < b.eps || (c.eps == b.eps && c.feature < b.feature));
 }
 
+// Scans features [f0, f1) of one job with the LDS table `tab` already filled:
+// groups of LPF lanes take one feature each, the g-th group-step of the
+// calling wave handles features f0 + (step0 + g * nsteps) * G + group.
+// Returns this lane's best candidate (the same in every lane of a group).
+template <int PREC, bool NARROW, int UNROLL, int LPF>
+__device__ __forceinline__ WgBest scan_range(const JobDev& jd, const typename ScanTypes<PREC>::W* tab, int64_t f0,
+                                             int64_t f1, int64_t step0, int64_t nsteps, double tp, double tn,
+                                             double2* __restrict__ ferr) {
+    constexpr int G = 64 / LPF;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / LPF, L = lane % LPF;
+    const int cnt = jd.g.q + (L < jd.g.rem ? 1 : 0);
+    const int nb = (jd.g.q + (jd.g.rem > 0 ? 1 : 0) + UNROLL - 1) / UNROLL;
+    WgBest best{DBL_MAX, -1, 0, -1};
+    // features past f1 read the padding unit (stride 0) and are dropped
+    auto row_of = [&](int64_t j, int& stride) -> const uint4* {
+        if (j < f1) { stride = LPF; return jd.keys + j * jd.g.row_units + L; }
+        stride = 0;
+        return jd.pad;
+    };
+    int64_t t = step0;
+    int64_t j = f0 + t * G + grp;
+    if (f0 + t * G >= f1) return best;
+    // batch 0 of the next feature is loaded before the current feature's
+    // group epilogue, so loads stay in flight across features
+    uint4 u[UNROLL];
+    int stride;
+    const uint4* p = row_of(j, stride);
+    load_batch<UNROLL>(u, p, stride, 0, nb, stride ? cnt : 0, jd.pad);
+    while (true) {
+        LaneAcc<PREC> a;
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
+        for (int b = 1; b < nb; ++b) {
+            load_batch<UNROLL>(u, p, stride, b, nb, stride ? cnt : 0, jd.pad);
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
+        }
+        const int64_t jcur = j;
+        t += nsteps;
+        const bool more = f0 + t * G < f1;
+        if (more) {
+            j = f0 + t * G + grp;
+            p = row_of(j, stride);
+            load_batch<UNROLL>(u, p, stride, 0, nb, stride ? cnt : 0, jd.pad);
+        }
+        const FeatureScan fs = finish_feature<PREC, LPF>(a, lane, tp, tn);
+        if (jcur < f1) {
+            if (ferr != nullptr && L == 0) ferr[jcur] = make_double2(fs.e_pos, fs.e_neg);
+            const bool pos = fs.e_pos <= fs.e_neg;
+            const double e = pos ? fs.e_pos : fs.e_neg;
+            if (e < best.eps) best = WgBest{e, jcur, pos ? 1 : -1, pos ? fs.lane_pos : fs.lane_neg};
+        }
+        if (!more) break;
+    }
+    return best;
+}
+
+// Reduces the groups' candidates of a workgroup (group leaders write theirs
+// to lds wb[]) and returns the workgroup's best in thread 0.
+template <int NG>
+__device__ __forceinline__ WgBest block_best(WgBest* wb, const WgBest& mine, int lpf) {
+    const int lane = threadIdx.x & 63;
+    if ((lane % lpf) == 0) wb[(threadIdx.x >> 6) * (64 / lpf) + lane / lpf] = mine;
+    __syncthreads();
+    WgBest b = wb[0];
+    if (threadIdx.x == 0)
+        for (int k = 1; k < NG; ++k)
+            if (better(wb[k], b)) b = wb[k];
+    return b;
+}
+
 // ---------------------------------------------------------------- scan kernel
-// Persistent: every workgroup fills its LDS weight table once, then each wave
-// takes features j = wave_id, wave_id + total_waves, ...  Each workgroup
-// leaves its best candidate (the first level of the argmin).
-template <int PREC, bool NARROW, int WG, int UNROLL, bool PIPE>
+// Persistent: every workgroup fills its LDS weight table once, then its waves
+// take group-steps of features; each workgroup leaves its best candidate
+// (the first level of the argmin).
+template <int PREC, bool NARROW, int WG, int UNROLL, int LPF>
 __global__ __launch_bounds__(WG) void k_scan(JobDev jd, double2* __restrict__ ferr) {
     using Wt = typename ScanTypes<PREC>::W;
-    __shared__ ScanLds<Wt, TabCap<PREC, NARROW>::value, WG / 64> lds;
+    constexpr int NG = (WG / 64) * (64 / LPF);
+    __shared__ ScanLds<Wt, TabCap<PREC, NARROW>::value, NG> lds;
     Wt* tab = lds.tab;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, wv = tid >> 6;
     WgBest best{DBL_MAX, -1, 0, -1};
     if (!jd.st->stopped) {
         const int par = jd.st->wpar;
         const double S = weight_sum(jd);
         double tp, tn;
-        fill_table<Wt>(jd, weights(jd, par), tab, 1.0 / S, WG, lds.sh, tp, tn);
+        fill_table<PREC>(jd, weights(jd, par), tab, 1.0 / S, WG, lds.sh, tp, tn);
         if (blockIdx.x == 0 && tid == 0) {
             jd.st->sum_w = S; jd.st->t_pos = tp; jd.st->t_neg = tn; jd.st->cur = par;
         }
-        const int cnt = jd.g.q + (lane < jd.g.rem ? 1 : 0);
-        const int nb = (jd.g.q + (jd.g.rem > 0 ? 1 : 0) + UNROLL - 1) / UNROLL;
         const int64_t total_waves = (int64_t)gridDim.x * (WG / 64);
-        int64_t j = (int64_t)blockIdx.x * (WG / 64) + wv;
-        // batch 0 of the next feature is loaded before the current feature's
-        // wave-level epilogue, so loads stay in flight across features
-        uint4 u[UNROLL];
-        if (j < jd.F) load_batch<UNROLL>(u, jd.keys + j * jd.g.row_units + lane, 0, nb, cnt, jd.pad);
-        for (; j < jd.F; j += total_waves) {
-            const uint4* p = jd.keys + j * jd.g.row_units + lane;
-            LaneAcc<PREC> a;
-#pragma unroll
-            for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
-            for (int b = 1; b < nb; ++b) {
-                load_batch<UNROLL>(u, p, b, nb, cnt, jd.pad);
-#pragma unroll
-                for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
-            }
-            const int64_t jn = j + total_waves;
-            if (jn < jd.F) load_batch<UNROLL>(u, jd.keys + jn * jd.g.row_units + lane, 0, nb, cnt, jd.pad);
-            const FeatureScan fs = finish_feature<PREC>(a, lane, tp, tn);
-            if (ferr != nullptr && lane == 0) ferr[j] = make_double2(fs.e_pos, fs.e_neg);
-            const bool pos = fs.e_pos <= fs.e_neg;
-            const double e = pos ? fs.e_pos : fs.e_neg;
-            if (e < best.eps) { best = WgBest{e, j, pos ? 1 : -1, pos ? fs.lane_pos : fs.lane_neg}; }
-        }
+        best = scan_range<PREC, NARROW, UNROLL, LPF>(jd, tab, 0, jd.F, (int64_t)blockIdx.x * (WG / 64) + wv,
+                                                     total_waves, tp, tn, ferr);
     }
-    if (lane == 0) lds.wb[wv] = best;
-    __syncthreads();
-    if (tid == 0) {
-        WgBest b = lds.wb[0];
-        for (int k = 1; k < WG / 64; ++k)
-            if (better(lds.wb[k], b)) b = lds.wb[k];
-        jd.wgb[blockIdx.x] = b;
-    }
+    const WgBest b = block_best<NG>(lds.wb, best, LPF);
+    if (tid == 0) jd.wgb[blockIdx.x] = b;
 }
 
 // ---------------------------------------------------------------- update kernel
@@ -103,26 +147,23 @@ __device__ inline int32_t index_at_rank(const JobDev& jd, int64_t j, int64_t r) 
     return (int32_t)((e & 1) ? i1 : i0);
 }
 
+// Longest lane segment: ceil(ceil(32767 / 8) / 16) units.
+constexpr int kMaxSeg = 257;
+
+template <typename Wt>
 struct UpdLds {
     WgBest wb[kUpdWg / 64];
     double sh[kUpdWg / 64];
+    Wt val[kMaxSeg * 8];       // table values of the winning lane's keys, rank order
+    uint32_t flags[kMaxSeg];   // run-end flags, one byte per unit
     int64_t k;
     int32_t theta;
     int32_t pad;
 };
 
-// Broadcast of lane src's value (src uniform across the wave).
-__device__ __forceinline__ float bcast(float v, int src) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
-}
-__device__ __forceinline__ double bcast(double v, int src) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, src);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-    return __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
-}
-__device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+// Inclusive prefix of v across the 64 lanes of a wave.
+__device__ __forceinline__ double wave_exclusive_incl(double v, int lane) {
+    return group_exclusive<64, double>(v, lane) + v;
 }
 
 // Every workgroup: the argmin over the scan's workgroup candidates (Section
@@ -137,7 +178,7 @@ __device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
 template <int PREC, bool NARROW>
 __global__ __launch_bounds__(kUpdWg) void k_update(JobDev jd, int n_wg) {
     using Wt = typename ScanTypes<PREC>::W;
-    __shared__ UpdLds lds;
+    __shared__ UpdLds<Wt> lds;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     JobState* st = jd.st;
     // 1. argmin over the scan workgroups' candidates
@@ -183,64 +224,122 @@ __global__ __launch_bounds__(kUpdWg) void k_update(JobDev jd, int n_wg) {
     // this workgroup's windows: values are loaded while the split is found
     const int64_t i = (int64_t)blockIdx.x * kUpdWg + tid;
     const int32_t f = i < n ? haar_value(jd.ii, jd.ii_stride, wp1, desc, i) : 0;
-    // 2. split rank and 3. threshold, by wave 0: lane r holds unit r of the
-    // winning lane's segment (window indices, table values, run-end flags);
-    // the running sum is then replayed in rank order with broadcasts.
-    if (wv == 0) {
-        const int L = b.lane;
-        const int cntL = L >= 0 ? jd.g.q + (L < jd.g.rem ? 1 : 0) : 0;
-        const int64_t seg0 = L >= 0 ? 8 * lane_start(jd.g, L) : 0;
-        uint32_t idx[8];
-        Wt val[8];
+    // 2. split rank: the winning lane's segment (table values, run-end flags)
+    // is staged in LDS by the whole workgroup; the running sum is then
+    // recomputed with the scan's arithmetic.
+    const int L = b.lane;
+    const int cntL = L >= 0 ? jd.g.q + (L < jd.g.rem ? 1 : 0) : 0;
+    for (int u = tid; u < cntL; u += kUpdWg) {
+        const uint4 q4 = jd.keys[j * jd.g.row_units + (int64_t)u * jd.g.lanes + L];
+        const uint32_t dw[4] = {q4.x, q4.y, q4.z, q4.w};
         uint32_t fb = 0;
-        if (lane < cntL) {
-            const uint4 u = jd.keys[j * jd.g.row_units + (int64_t)lane * 64 + L];
-            const uint32_t dw[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                uint32_t f0, f1;
-                decode_pair(jd.g.narrow, dw[h], idx[2 * h], f0, idx[2 * h + 1], f1);
-                fb |= (f0 << (2 * h)) | (f1 << (2 * h + 1));
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                val[e] = idx[e] < (uint32_t)n ? table_value<Wt>(w_in[idx[e]], rS, idx[e] < (uint32_t)l) : (Wt)0;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) { idx[e] = 0; val[e] = (Wt)0; }
+        for (int h = 0; h < 4; ++h) {
+            uint32_t i0, f0, i1, f1;
+            decode_pair(jd.g.narrow, dw[h], i0, f0, i1, f1);
+            fb |= (f0 << (2 * h)) | (f1 << (2 * h + 1));
+            lds.val[u * 8 + 2 * h] = i0 < (uint32_t)n ? table_value<PREC>(w_in[i0], rS, i0 < (uint32_t)l) : (Wt)0;
+            lds.val[u * 8 + 2 * h + 1] = i1 < (uint32_t)n ? table_value<PREC>(w_in[i1], rS, i1 < (uint32_t)l) : (Wt)0;
         }
-        int64_t k = 0;
+        lds.flags[u] = fb;
+    }
+    __syncthreads();
+    int64_t k = 0;
+    if constexpr (ExactSums<PREC>::value) {
+        // exact running sums: the lane's prefix at every key is computed in
+        // parallel (unit sums, a block scan of them, then within the unit) and
+        // equals the scan's sequential value bit for bit
         if (L >= 0) {
-            LaneAcc<PREC> a;
-            decltype(a.add(Wt(0))) ext = pol > 0 ? -4 : 4;
-            int ext_rank = -1;
-            for (int r = 0; r < cntL; ++r) {
-                const uint32_t fr = bcast(fb, r);
+            double us[2] = {0.0, 0.0};
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const auto v = a.add(bcast(val[e], r));
-                    if (((fr >> e) & 1u) && (pol > 0 ? v > ext : v < ext)) { ext = v; ext_rank = 8 * r + e; }
+            for (int h = 0; h < 2; ++h) {
+                const int u = tid + h * kUpdWg;
+                if (u < cntL)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) us[h] += (double)lds.val[u * 8 + e];
+            }
+            // exclusive prefix over units: 2 units per thread in order tid, tid + 256
+            const double tsum = us[0];
+            double incl = wave_exclusive_incl(tsum, lane);
+            if (lane == 63) lds.sh[wv] = incl;
+            __syncthreads();
+            double wbase = 0.0, all0 = 0.0;
+            for (int q = 0; q < kUpdWg / 64; ++q) { if (q < wv) wbase += lds.sh[q]; all0 += lds.sh[q]; }
+            double ex0 = wbase + incl - tsum;          // prefix before unit tid
+            __syncthreads();
+            double incl1 = wave_exclusive_incl(us[1], lane);
+            if (lane == 63) lds.sh[wv] = incl1;
+            __syncthreads();
+            double wbase1 = all0;
+            for (int q = 0; q < wv; ++q) wbase1 += lds.sh[q];
+            double ex1 = wbase1 + incl1 - us[1];       // prefix before unit tid + 256
+            // candidates: extreme value, then the smallest rank
+            double best_v = pol > 0 ? -4.0 : 4.0;
+            int best_r = 0x7FFFFFFF;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int u = tid + h * kUpdWg;
+                if (u < cntL) {
+                    double acc = h == 0 ? ex0 : ex1;
+                    const uint32_t fr = lds.flags[u];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        acc += (double)lds.val[u * 8 + e];
+                        if ((fr >> e) & 1u) {
+                            const bool c = pol > 0 ? acc > best_v : acc < best_v;
+                            if (c) { best_v = acc; best_r = u * 8 + e; }
+                        }
+                    }
                 }
             }
-            k = seg0 + ext_rank + 1;
-        }
-        // window at the rank just above (p = +1) or at (p = -1) the split
-        const int64_t rk = pol > 0 ? (k < n ? k : n - 1) : (k > 0 ? k - 1 : 0);
-        int32_t wi;
-        if (L >= 0 && rk >= seg0 && rk < seg0 + 8 * cntL) {
-            const int r = (int)((rk - seg0) >> 3), e = (int)((rk - seg0) & 7);
-            uint32_t pick = 0;
+            // block reduction: extreme value, ties to the smaller rank
 #pragma unroll
-            for (int q = 0; q < 8; ++q) pick = q == e ? idx[q] : pick;
-            wi = (int32_t)bcast(pick, r);
-        } else {
-            wi = index_at_rank(jd, j, rk);
+            for (int o = 32; o; o >>= 1) {
+                const double ov = __shfl_xor(best_v, o);
+                const int orr = __shfl_xor(best_r, o);
+                const bool c = (pol > 0 ? ov > best_v : ov < best_v) || (ov == best_v && orr < best_r);
+                if (c) { best_v = ov; best_r = orr; }
+            }
+            __syncthreads();
+            if (lane == 0) { lds.wb[wv].eps = best_v; lds.wb[wv].lane = best_r; }
+            __syncthreads();
+            if (tid == 0) {
+                for (int q = 1; q < kUpdWg / 64; ++q) {
+                    const double ov = lds.wb[q].eps;
+                    const int orr = lds.wb[q].lane;
+                    const bool c = (pol > 0 ? ov > best_v : ov < best_v) || (ov == best_v && orr < best_r);
+                    if (c) { best_v = ov; best_r = orr; }
+                }
+                k = 8 * lane_start(jd.g, L) + best_r + 1;
+            }
         }
-        if (lane == 0) {
-            const int32_t v = haar_value(jd.ii, jd.ii_stride, wp1, desc, wi);
-            lds.k = k;
-            lds.theta = pol > 0 ? (k < n ? v : v + 1) : (k > 0 ? v : v - 1);
+    } else if (tid == 0 && L >= 0) {
+        // rounded running sums: replayed in the scan's order by one thread
+        LaneAcc<PREC> a;
+        decltype(a.add(Wt(0))) ext = pol > 0 ? -4 : 4;
+        int ext_rank = -1;
+        for (int r = 0; r < cntL; ++r) {
+            Wt v8[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v8[e] = lds.val[r * 8 + e];
+            const uint32_t fr = lds.flags[r];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const auto v = a.add(v8[e]);
+                const bool c = ((fr >> e) & 1u) && (pol > 0 ? v > ext : v < ext);
+                ext = c ? v : ext;
+                ext_rank = c ? 8 * r + e : ext_rank;
+            }
         }
+        k = 8 * lane_start(jd.g, L) + ext_rank + 1;
+    }
+    if (tid == 0) {
+        // 3. threshold from the window at the rank just above (p = +1) or at
+        // (p = -1) the split
+        const int64_t rk = pol > 0 ? (k < n ? k : n - 1) : (k > 0 ? k - 1 : 0);
+        const int32_t v = haar_value(jd.ii, jd.ii_stride, wp1, desc, index_at_rank(jd, j, rk));
+        lds.k = k;
+        lds.theta = pol > 0 ? (k < n ? v : v + 1) : (k > 0 ? v : v - 1);
     }
     __syncthreads();
     // 4. beta, alpha (FP64); eps = 0 is clamped to the floor
@@ -285,30 +384,33 @@ __global__ __launch_bounds__(kUpdWg) void k_update(JobDev jd, int n_wg) {
 }
 
 // ---------------------------------------------------------------- launchers
-// Launch schedules (workgroup size, units per batch, pipelined loads).
-struct Schedule { int wg, unroll, pipe; };
+// Launch schedules: workgroup size, units per batch, lanes per feature.
+struct Schedule { int wg, unroll, lanes; };
 static const Schedule kSchedules[] = {
-    {512, 10, 0}, {512, 8, 0}, {512, 6, 0}, {512, 15, 0}, {512, 4, 0}, {1024, 10, 0}, {512, 5, 0}, {256, 10, 0},
+    {512, 8, 16}, {512, 10, 16}, {512, 6, 16}, {512, 4, 16}, {1024, 8, 16}, {512, 8, 32}, {512, 10, 64}, {256, 8, 16},
 };
 constexpr int kNumSchedules = (int)(sizeof(kSchedules) / sizeof(kSchedules[0]));
 
 template <int PREC, bool NARROW>
 static const void* scan_kernel_ptr(int schedule) {
     switch (schedule) {
-    case 1: return (const void*)k_scan<PREC, NARROW, 512, 8, false>;
-    case 2: return (const void*)k_scan<PREC, NARROW, 512, 6, false>;
-    case 3: return (const void*)k_scan<PREC, NARROW, 512, 15, false>;
-    case 4: return (const void*)k_scan<PREC, NARROW, 512, 4, false>;
-    case 5: return (const void*)k_scan<PREC, NARROW, 1024, 10, false>;
-    case 6: return (const void*)k_scan<PREC, NARROW, 512, 5, false>;
-    case 7: return (const void*)k_scan<PREC, NARROW, 256, 10, false>;
-    default: return (const void*)k_scan<PREC, NARROW, 512, 10, false>;
+    case 1: return (const void*)k_scan<PREC, NARROW, 512, 10, 16>;
+    case 2: return (const void*)k_scan<PREC, NARROW, 512, 6, 16>;
+    case 3: return (const void*)k_scan<PREC, NARROW, 512, 4, 16>;
+    case 4: return (const void*)k_scan<PREC, NARROW, 1024, 8, 16>;
+    case 5: return (const void*)k_scan<PREC, NARROW, 512, 8, 32>;
+    case 6: return (const void*)k_scan<PREC, NARROW, 512, 10, 64>;
+    case 7: return (const void*)k_scan<PREC, NARROW, 256, 8, 16>;
+    default: return (const void*)k_scan<PREC, NARROW, 512, 8, 16>;
     }
 }
 
 int scan_schedule_count() { return kNumSchedules; }
 int scan_schedule_wg(int schedule) {
     return kSchedules[(schedule >= 0 && schedule < kNumSchedules) ? schedule : 0].wg;
+}
+int scan_schedule_lanes(int schedule) {
+    return kSchedules[(schedule >= 0 && schedule < kNumSchedules) ? schedule : 0].lanes;
 }
 
 const void* scan_kernel(int precision, bool narrow, int schedule) {
@@ -340,7 +442,8 @@ int scan_plan(ScanPlan& p, int precision, bool narrow, int schedule, int64_t n, 
         return BOOST_E_INVALID;
     }
     int64_t grid = (int64_t)per_cu * num_cu;
-    const int64_t max_grid = (F + p.wg / 64 - 1) / (p.wg / 64);   // at least one feature per wave
+    const int64_t per_wg = (int64_t)(p.wg / 64) * (64 / scan_schedule_lanes(schedule));   // features per workgroup step
+    const int64_t max_grid = (F + per_wg - 1) / per_wg;
     if (grid > max_grid) grid = max_grid;
     if (grid > kMaxScanGrid) grid = kMaxScanGrid;
     p.grid = (int)grid;

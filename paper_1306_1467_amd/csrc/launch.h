@@ -20,6 +20,7 @@ struct ScanPlan {
 // k_scan.hip
 int scan_schedule_count();
 int scan_schedule_wg(int schedule);
+int scan_schedule_lanes(int schedule);
 int64_t scan_table_capacity(int precision, bool narrow);
 int scan_plan(ScanPlan& p, int precision, bool narrow, int schedule, int64_t n, int64_t F, int num_cu);
 int scan_launch(const ScanPlan& p, const JobDev& jd, double2* ferr, hipStream_t s);

@@ -189,75 +189,89 @@ __device__ __forceinline__ float read_lane(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// Exclusive prefix of the lane totals across the wave, in a fixed order:
-// inclusive scan within rows of 16 (shifts 1, 2, 4, 8), then row 0's total
-// into row 1 and row 2's into row 3, then rows 0-1's total into rows 2-3;
-// finally a shift by one lane.
-template <typename A>
-__device__ __forceinline__ A wave_exclusive(A tot) {
+// Exclusive prefix of the lane totals within each group of LPF lanes (16, 32
+// or 64), in a fixed order: inclusive scan within rows of 16 (shifts 1, 2, 4,
+// 8); for groups of 32 or 64, row 0's total into row 1 and row 2's into row
+// 3; for 64, rows 0-1's total into rows 2-3; finally a shift by one lane with
+// zero at each group's first lane.
+template <int LPF, typename A>
+__device__ __forceinline__ A group_exclusive(A tot, int lane) {
     A v = tot;
     v += dpp<0x111, 0xF, 0xF, true>(v, (A)0);
     v += dpp<0x112, 0xF, 0xF, true>(v, (A)0);
     v += dpp<0x114, 0xF, 0xF, true>(v, (A)0);
     v += dpp<0x118, 0xF, 0xF, true>(v, (A)0);
-    v += dpp<0x142, 0xA, 0xF, false>(v, (A)0);
-    v += dpp<0x143, 0xC, 0xF, false>(v, (A)0);
-    return dpp<0x138, 0xF, 0xF, true>(v, (A)0);
+    if constexpr (LPF >= 32) v += dpp<0x142, 0xA, 0xF, false>(v, (A)0);
+    if constexpr (LPF == 64) v += dpp<0x143, 0xC, 0xF, false>(v, (A)0);
+    const A ex = dpp<0x138, 0xF, 0xF, true>(v, (A)0);   // wave_shr:1
+    return (lane & (LPF - 1)) == 0 ? (A)0 : ex;
 }
 
-// Wave-wide maximum (MAX) or minimum, the same value in every lane.
-template <bool MAX, typename A>
-__device__ __forceinline__ A wave_extreme(A v) {
+// Maximum (MAX) or minimum over each group of LPF lanes, in every lane of the group.
+template <int LPF, bool MAX, typename A>
+__device__ __forceinline__ A group_extreme(A v, int lane) {
     auto op = [](A a, A b) { return MAX ? fmax(a, b) : fmin(a, b); };
     v = op(v, dpp<0xB1, 0xF, 0xF, false>(v, v));    // quad_perm [1,0,3,2]
     v = op(v, dpp<0x4E, 0xF, 0xF, false>(v, v));    // quad_perm [2,3,0,1]
     v = op(v, dpp<0x141, 0xF, 0xF, false>(v, v));   // row_half_mirror
-    v = op(v, dpp<0x140, 0xF, 0xF, false>(v, v));   // row_mirror
-    v = op(v, dpp<0x142, 0xA, 0xF, false>(v, v));   // row_bcast:15
-    v = op(v, dpp<0x143, 0xC, 0xF, false>(v, v));   // row_bcast:31
-    return read_lane(v, 63);
+    v = op(v, dpp<0x140, 0xF, 0xF, false>(v, v));   // row_mirror: every lane has its row's extreme
+    if constexpr (LPF == 16) {
+        return v;
+    } else if constexpr (LPF == 32) {
+        v = op(v, dpp<0x142, 0xA, 0xF, false>(v, v));   // rows 1 and 3 now hold their pair's extreme
+        const A lo = read_lane(v, 31), hi = read_lane(v, 63);
+        return lane < 32 ? lo : hi;
+    } else {
+        v = op(v, dpp<0x142, 0xA, 0xF, false>(v, v));
+        v = op(v, dpp<0x143, 0xC, 0xF, false>(v, v));
+        return read_lane(v, 63);
+    }
 }
 
-// Result of one feature's scan, identical in every lane of the wave.
+// Result of one feature's scan, identical in every lane of its group.
 struct FeatureScan {
-    double e_pos, e_neg;   // best error for p = +1 / p = -1
-    int lane_pos, lane_neg;  // first lane holding the extreme (-1: the empty split k = 0)
+    double e_pos, e_neg;     // best error for p = +1 / p = -1
+    int lane_pos, lane_neg;  // first lane (within the group) holding the extreme (-1: the empty split k = 0)
 };
 
-// Loads batch b (UNROLL units) of one lane's segment.  All batches but the
-// last (nb - 1) are full for every lane; in the last one, units past the
-// lane's segment come from `pad` (a unit of padding keys, cache resident), so
-// the loads need no branches.
+// Loads batch b (UNROLL units) of one lane's segment; units are `stride`
+// apart.  All batches but the last (nb - 1) are full for every lane; in the
+// last one, units past the lane's segment come from `pad` (a unit of padding
+// keys, cache resident), so the loads need no branches.
 template <int UNROLL>
-__device__ __forceinline__ void load_batch(uint4* u, const uint4* __restrict__ p, int b, int nb, int cnt,
+__device__ __forceinline__ void load_batch(uint4* u, const uint4* __restrict__ p, int stride, int b, int nb, int cnt,
                                            const uint4* __restrict__ pad) {
     if (b + 1 < nb) {
 #pragma unroll
-        for (int k = 0; k < UNROLL; ++k) u[k] = ld_stream(p + 64 * (b * UNROLL + k));
+        for (int k = 0; k < UNROLL; ++k) u[k] = ld_stream(p + stride * (b * UNROLL + k));
     } else {
 #pragma unroll
         for (int k = 0; k < UNROLL; ++k) {
             const int r = b * UNROLL + k;
-            u[k] = ld_stream(r < cnt ? p + 64 * r : pad);
+            u[k] = ld_stream(r < cnt ? p + stride * r : pad);
         }
     }
 }
 
-// Wave-level end of one feature's scan: lane totals -> exclusive prefix ->
-// global extremes of the running sum at run ends -> errors for both polarities.
-template <int PREC>
+// Group-level end of one feature's scan: lane totals -> exclusive prefix ->
+// extremes of the running sum at run ends -> errors for both polarities.
+template <int PREC, int LPF>
 __device__ __forceinline__ FeatureScan finish_feature(const LaneAcc<PREC>& a, int lane, double t_pos, double t_neg) {
     using A = typename ScanTypes<PREC>::A;
-    const A base = wave_exclusive<A>((A)a.total());
+    const A base = group_exclusive<LPF, A>((A)a.total(), lane);
     const A lmx = base + (A)a.vmax();
     const A lmn = base + (A)a.vmin();
-    A cmx = wave_extreme<true>(lmx);
-    A cmn = wave_extreme<false>(lmn);
+    A cmx = group_extreme<LPF, true>(lmx, lane);
+    A cmn = group_extreme<LPF, false>(lmn, lane);
+    const int sh = (lane / LPF) * LPF;
+    const unsigned long long gm = LPF == 64 ? ~0ull : ((1ull << LPF) - 1ull);
     FeatureScan r;
     // k = 0 (nothing below the threshold) is always realisable: D_0 = 0, and
     // it is the smallest split, so it wins ties.
-    r.lane_pos = cmx > (A)0 ? __ffsll(__ballot(lmx == cmx)) - 1 : -1;
-    r.lane_neg = cmn < (A)0 ? __ffsll(__ballot(lmn == cmn)) - 1 : -1;
+    const unsigned long long bx = (__ballot(lmx == cmx) >> sh) & gm;
+    const unsigned long long bn = (__ballot(lmn == cmn) >> sh) & gm;
+    r.lane_pos = cmx > (A)0 ? __ffsll(bx) - 1 : -1;
+    r.lane_neg = cmn < (A)0 ? __ffsll(bn) - 1 : -1;
     cmx = fmax(cmx, (A)0);
     cmn = fmin(cmn, (A)0);
     r.e_pos = (double)((A)t_pos - cmx);
@@ -297,11 +311,29 @@ __device__ __forceinline__ double weight_sum(const JobDev& jd) {
     return __shfl(p, 0);
 }
 
+// Modes whose running sums are exact: every table value is a multiple of
+// 2^-52 and every prefix has magnitude < 2 (the table's absolute values sum
+// to ~1), so each FP64 partial sum is exactly representable and the result
+// does not depend on the summation order.
+template <int PREC>
+struct ExactSums { static constexpr bool value = PREC == BOOST_PREC_FP32_WIDE || PREC == BOOST_PREC_FP64; };
+
 // One entry of the scan's signed weight table: the normalised weight
-// w_i * (1 / S) rounded to the table type, negated for negatives.
-template <typename Wt>
-__device__ __forceinline__ Wt table_value(double w, double rS, bool positive) {
-    const Wt wn = (Wt)(w * rS);
+// w_i * (1 / S) rounded to the table type (and, in the exact modes, to a
+// multiple of 2^-52: FP32 values of magnitude >= 2^-28 already are one;
+// smaller ones move by at most 2^-53), negated for negatives.
+template <int PREC>
+__device__ __forceinline__ typename ScanTypes<PREC>::W table_value(double w, double rS, bool positive) {
+    using Wt = typename ScanTypes<PREC>::W;
+    constexpr double kGrid = 4503599627370496.0;          // 2^52
+    constexpr double kInvGrid = 1.0 / 4503599627370496.0;  // 2^-52
+    Wt wn = (Wt)(w * rS);
+    if constexpr (PREC == BOOST_PREC_FP64) {
+        wn = rint(wn * kGrid) * kInvGrid;
+    } else if constexpr (PREC == BOOST_PREC_FP32_WIDE) {
+        if (wn < (Wt)3.7252902984619140625e-9f)           // 2^-28
+            wn = (Wt)(rint((double)wn * kGrid) * kInvGrid);
+    }
     return positive ? wn : -wn;
 }
 
@@ -310,12 +342,13 @@ __device__ __forceinline__ Wt table_value(double w, double rS, bool positive) {
 // T- of the table (one fixed-order pass: thread t < 256 adds entries t, t +
 // 256, ... into T+ or T-, then a fixed butterfly per wave and the four wave
 // sums in order).  Every workgroup computes the same values.
-template <typename Wt>
-__device__ __forceinline__ void fill_table(const JobDev& jd, const double* w, Wt* tab, double rS, int nt, double* sh,
-                                           double& tp, double& tn) {
+template <int PREC>
+__device__ __forceinline__ void fill_table(const JobDev& jd, const double* w, typename ScanTypes<PREC>::W* tab,
+                                           double rS, int nt, double* sh, double& tp, double& tn) {
+    using Wt = typename ScanTypes<PREC>::W;
     const int64_t n = jd.g.n;
     const int64_t l = jd.st->n_pos;
-    for (int64_t i = threadIdx.x; i < n; i += nt) tab[i] = table_value<Wt>(w[i], rS, i < l);
+    for (int64_t i = threadIdx.x; i < n; i += nt) tab[i] = table_value<PREC>(w[i], rS, i < l);
     if (threadIdx.x == 0) tab[n] = (Wt)0;
     __syncthreads();
     double p = 0.0, q = 0.0;
