@@ -8,8 +8,10 @@ features, the threshold, beta / alpha and the weight update.  The one-time
 preparation (integral images, feature values, per-feature sort) runs before
 the timed region and is reported separately as init_ms.
 
-Prints one JSON line.  --batched adds the batched-jobs measurement
-(32 uneven jobs, jobs*rounds/s, against the same jobs run one at a time).
+Prints one JSON line, which also carries the batched-jobs measurement
+(32 uneven jobs by default, jobs*rounds/s, against the same jobs run one at
+a time through the single-job path) and the FP64 oracle's round time on the
+host cores for a bounded sample of features.
 """
 from __future__ import annotations
 
@@ -139,49 +141,54 @@ def run_single(args, torch, vb, synth):
     return out, images, labels
 
 
-def run_batched(args, torch, vb, synth):
+def run_batched(config, args, torch, vb, synth):
+    """Jobs of a batched workload trained together (one scan + one update
+    launch per round for all jobs) against the same jobs trained one at a
+    time through the single-job path, same precision and schedule."""
     import numpy as np
-    from paper_1306_1467_amd import batch as vbatch
-    specs = synth.config_jobs(3)
+    specs = synth.config_jobs(config)
     data = [s.make() for s in specs]
-    rounds = args.batch_rounds
-    # plain: each job alone through the single-job path
+    rounds = args.batch_rounds or specs[0].rounds
+    prec = args.batch_precision
+    # plain: each job alone; one untimed round first (graph capture), as below
     t_plain = 0.0
-    plain_recs = []
-    for (images, labels) in data:
-        tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=args.batch_precision)
-        vb.boost_train(tr.ctx, 1, False)      # warm the graph
+    plain = []
+    for images, labels in data:
+        tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=prec, schedule_id=args.schedule)
+        vb.boost_train(tr.ctx, 1, False)
         tr.stream.synchronize()
         t0 = time.perf_counter()
-        r = vb.boost_train(tr.ctx, rounds, True)
+        plain.append(vb.boost_train(tr.ctx, rounds, True))
         t_plain += time.perf_counter() - t0
-        plain_recs.append(r)
         tr.close()
         del tr
         torch.cuda.empty_cache()
-    bt = vbatch.BatchTrainer([(torch.from_numpy(i), torch.from_numpy(l)) for i, l in data],
-                             precision=args.batch_precision)
+    t0 = time.perf_counter()
+    bt = vb.BatchTrainer([(torch.from_numpy(i), torch.from_numpy(l)) for i, l in data], precision=prec,
+                         schedule_id=args.schedule)
+    bt.sync()
+    init_s = time.perf_counter() - t0
     bt.train(1, False)
     bt.sync()
     t0 = time.perf_counter()
     recs = bt.train(rounds, True)
     t_batch = time.perf_counter() - t0
-    # plain ran one extra warm round per job; compare rounds 1..rounds
-    same = all(np.array_equal(recs[:, k]["feature"], plain_recs[k]["feature"][:0] if False else
-                              _shifted(plain_recs[k], recs[:, k])) for k in range(len(data)))
+    same = all(recs[:, k].tobytes() == plain[k].tobytes() for k in range(len(data)))
+    keys = sum(vb.boost_feature_count(vb.feature_set(s.size)) * s.n for s in specs)
     jr = len(data) * rounds
     bt.close()
-    return {"jobs": len(data), "rounds": rounds, "precision": args.batch_precision,
-            "batched_jobs_rounds_per_s": round(jr / t_batch, 1),
-            "plain_jobs_rounds_per_s": round(jr / t_plain, 1),
+    del bt
+    torch.cuda.empty_cache()
+    return {"workload": f"{len(data)} jobs, " + ("24x24 windows" if config == 3 else "16/20/24/28 windows")
+                        + f", {min(s.n for s in specs):,}-{max(s.n for s in specs):,} windows per job",
+            "jobs": len(data), "rounds": rounds, "precision": prec, "keys_per_round": keys,
+            "batched_jobs_rounds_per_s": round(jr / t_batch, 2),
+            "plain_jobs_rounds_per_s": round(jr / t_plain, 2),
             "speedup_vs_plain": round(t_plain / t_batch, 3),
+            "batched_ms_per_round": round(t_batch * 1e3 / rounds, 3),
+            "batched_key_GBps": round(keys * 2 * rounds / t_batch / 1e9, 1),
+            "batched_init_s": round(init_s, 2),
             "stumps_identical_to_plain": bool(same)}
-
-
-def _shifted(plain, batched):
-    import numpy as np
-    return np.array_equal(plain["feature"], batched["feature"]) and \
-        np.array_equal(plain["error_raw"], batched["error_raw"])
 
 
 def main():
@@ -194,8 +201,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-features", type=int, default=12000)
     ap.add_argument("--cpu-rounds", type=int, default=2)
-    ap.add_argument("--batched", action="store_true")
-    ap.add_argument("--batch-rounds", type=int, default=50)
+    ap.add_argument("--batched-configs", default="3",
+                    help="comma list of batched workloads to measure (3: 32 jobs, 4: 64 jobs); empty for none")
+    ap.add_argument("--batch-rounds", type=int, default=0, help="rounds per batched job (0: the workload's own)")
     ap.add_argument("--batch-precision", default="fp32_wide")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run one device copy of this many GiB first (counter calibration)")
@@ -242,8 +250,8 @@ def main():
         "roofline": res["roofline"],
         "last_round": res["last_round"],
     }
-    if args.batched:
-        line["batched"] = run_batched(args, torch, vb, synth)
+    for cfg in [c for c in args.batched_configs.split(",") if c.strip()]:
+        line[f"batched_config{int(cfg)}"] = run_batched(int(cfg), args, torch, vb, synth)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(images, labels, args.cpu_features, args.cpu_rounds)
     else:

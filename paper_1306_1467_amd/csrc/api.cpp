@@ -58,6 +58,86 @@ static bool make_layout(int64_t n, const boost_feature_set* fs, Layout& L) {
     return true;
 }
 
+int check_job_args(int64_t n, const boost_feature_set* fs, const boost_options* o) {
+    if (n < 2 || n > kMaxN) { set_error("n must be in 2..32767"); return BOOST_E_INVALID; }
+    if (!valid_feature_set(fs)) { set_error("invalid feature set (window 1..32, non-empty 5-bit type mask)"); return BOOST_E_INVALID; }
+    if (!valid_options(o)) { set_error("invalid options"); return BOOST_E_INVALID; }
+    if (host_feature_count(fs) <= 0) { set_error("the feature set has no feature that fits the window"); return BOOST_E_INVALID; }
+    if (o->precision == BOOST_PREC_FP64 && n > kMaxFp64N) {
+        set_error("FP64 precision supports at most 20000 windows (the weight table lives in LDS)");
+        return BOOST_E_INVALID;
+    }
+    return BOOST_OK;
+}
+
+size_t job_bytes(int64_t n, const boost_feature_set* fs) {
+    Layout L;
+    if (!make_layout(n, fs, L)) return 0;
+    return L.total;
+}
+
+static int sync_state(hipStream_t s, const JobState* d_st, JobState& st) {
+    VJB_HIP(hipStreamSynchronize(s));
+    VJB_HIP(hipMemcpy(&st, d_st, sizeof(JobState), hipMemcpyDeviceToHost));
+    return BOOST_OK;
+}
+
+// Lays one job out in ws (job_bytes(n, fs) bytes) and runs its one-time
+// preparation: ingest, integral images, per-feature evaluate + sort + keys,
+// initial weights.  Synchronises (label validation needs the count).
+int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, const boost_options* o,
+              const uint8_t* d_images, const uint8_t* d_labels, int num_cu, hipStream_t s) {
+    Layout L;
+    make_layout(n, fs, L);
+    JobDev& jd = h.jd;
+    jd = JobDev{};
+    jd.keys = (const uint4*)(ws + L.keys);
+    jd.ii = (const int32_t*)(ws + L.ii);
+    jd.ftab = (const uint32_t*)(ws + L.ftab);
+    jd.w = (double*)(ws + L.w);
+    jd.wpart = (double*)(ws + L.wpart);
+    jd.wgb = (WgBest*)(ws + L.wgbest);
+    jd.pad = (const uint4*)(ws + L.pad);
+    jd.st = (JobState*)(ws + L.st);
+    jd.ring = (boost_stump*)(ws + L.ring);
+    jd.perm = (const int32_t*)(ws + L.perm);
+    jd.inv = (const int32_t*)(ws + L.inv);
+    jd.g = make_geom(n, scan_schedule_lanes(o->schedule_id));
+    jd.F = host_feature_count(fs);
+    jd.ii_stride = ii_stride_of(n);
+    jd.W = fs->window_w;
+    jd.H = fs->window_h;
+    jd.precision = o->precision;
+    jd.on_perfect = o->on_perfect;
+    jd.n_part = (int32_t)((n + kUpdWg - 1) / kUpdWg);
+    jd.unused = 0;
+    jd.eps_floor = o->eps_floor;
+    h.wtmp = (double*)(ws + L.wtmp);
+    h.cls = (StumpDev*)(ws + L.cls);
+    h.scratch = sort_scratch_bytes(n) ? (uint64_t*)(ws + L.scratch) : nullptr;
+
+    std::vector<uint32_t> ftab((size_t)jd.F);
+    host_feature_table(fs, ftab.data());
+    const uint32_t pd = pad_dword(jd.g);
+    const uint32_t pad_unit[4] = {pd, pd, pd, pd};
+    VJB_HIP(hipMemcpyAsync((void*)jd.ftab, ftab.data(), ftab.size() * 4, hipMemcpyHostToDevice, s));
+    VJB_HIP(hipMemcpyAsync((void*)jd.pad, pad_unit, 16, hipMemcpyHostToDevice, s));
+    VJB_HIP(hipMemsetAsync(jd.st, 0, sizeof(JobState), s));
+    int rc;
+    if ((rc = ingest_launch(jd, d_labels, n, s)) != BOOST_OK) return rc;
+    JobState st;
+    if ((rc = sync_state(s, jd.st, st)) != BOOST_OK) return rc;   // also retires the host copies above
+    if (st.label_error) { set_error("labels must be 0 or 1"); return BOOST_E_INVALID; }
+    if (st.n_pos == 0 || st.n_pos == n) {
+        set_error("both classes need at least one window (1/(2l) and 1/(2m) must exist)");
+        return BOOST_E_INVALID;
+    }
+    if ((rc = integral_launch(jd, d_images, s)) != BOOST_OK) return rc;
+    if ((rc = sort_launch(jd, h.scratch, num_cu, s)) != BOOST_OK) return rc;
+    if ((rc = init_weights_launch(jd, s)) != BOOST_OK) return rc;
+    return BOOST_OK;
+}
+
 }  // namespace vjb
 
 using namespace vjb;
@@ -110,41 +190,22 @@ int boost_schedule_count(int32_t precision) {
     return scan_schedule_count();
 }
 
-static int check_init_args(int64_t n, const boost_feature_set* fs, const boost_options* o) {
-    if (n < 2 || n > kMaxN) { set_error("n must be in 2..32767"); return BOOST_E_INVALID; }
-    if (!valid_feature_set(fs)) { set_error("invalid feature set (window 1..32, non-empty 5-bit type mask)"); return BOOST_E_INVALID; }
-    if (!valid_options(o)) { set_error("invalid options"); return BOOST_E_INVALID; }
-    if (host_feature_count(fs) <= 0) { set_error("the feature set has no feature that fits the window"); return BOOST_E_INVALID; }
-    if (o->precision == BOOST_PREC_FP64 && n > kMaxFp64N) {
-        set_error("FP64 precision supports at most 20000 windows (the weight table lives in LDS)");
-        return BOOST_E_INVALID;
-    }
-    return BOOST_OK;
-}
-
 size_t boost_workspace_bytes(int64_t n, const boost_feature_set* fs, const boost_options* o) {
-    if (check_init_args(n, fs, o) != BOOST_OK) return 0;
-    Layout L;
-    if (!make_layout(n, fs, L)) return 0;
-    return L.total;
+    if (check_job_args(n, fs, o) != BOOST_OK) return 0;
+    return job_bytes(n, fs);
 }
 
-static int sync_and_state(boost_ctx* c, JobState& st) {
-    VJB_HIP(hipStreamSynchronize(c->stream));
-    VJB_HIP(hipMemcpy(&st, c->jd.st, sizeof(JobState), hipMemcpyDeviceToHost));
-    return BOOST_OK;
-}
+static int sync_and_state(boost_ctx* c, JobState& st) { return sync_state(c->stream, c->jd.st, st); }
 
 int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels, int64_t n,
                const boost_feature_set* fs, const boost_options* o, void* d_workspace, size_t workspace_bytes) {
     if (!out || !d_images || !d_labels || !d_workspace) { set_error("NULL pointer argument"); return BOOST_E_INVALID; }
     *out = nullptr;
-    int rc = check_init_args(n, fs, o);
+    int rc = check_job_args(n, fs, o);
     if (rc != BOOST_OK) return rc;
-    Layout L;
-    make_layout(n, fs, L);
-    if (workspace_bytes < L.total) {
-        set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
+    const size_t need = job_bytes(n, fs);
+    if (workspace_bytes < need) {
+        set_error("workspace too small: need " + std::to_string(need) + " bytes");
         return BOOST_E_NOMEM;
     }
     boost_ctx* c = new boost_ctx();
@@ -159,55 +220,14 @@ int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels
         set_error("no HIP device");
         return fail(BOOST_E_DEVICE);
     }
-    char* ws = (char*)d_workspace;
-    JobDev& jd = c->jd;
-    jd.keys = (const uint4*)(ws + L.keys);
-    jd.ii = (const int32_t*)(ws + L.ii);
-    jd.ftab = (const uint32_t*)(ws + L.ftab);
-    jd.w = (double*)(ws + L.w);
-    jd.wpart = (double*)(ws + L.wpart);
-    jd.wgb = (WgBest*)(ws + L.wgbest);
-    jd.n_part = (int32_t)((n + kUpdWg - 1) / kUpdWg);
-    jd.pad = (const uint4*)(ws + L.pad);
-    jd.unused = 0;
-    jd.st = (JobState*)(ws + L.st);
-    jd.ring = (boost_stump*)(ws + L.ring);
-    jd.perm = (const int32_t*)(ws + L.perm);
-    jd.inv = (const int32_t*)(ws + L.inv);
-    jd.g = make_geom(n, scan_schedule_lanes(o->schedule_id));
-    jd.F = c->F;
-    jd.ii_stride = ii_stride_of(n);
-    jd.W = fs->window_w;
-    jd.H = fs->window_h;
-    jd.precision = o->precision;
-    jd.on_perfect = o->on_perfect;
-    jd.eps_floor = o->eps_floor;
-    c->wtmp = (double*)(ws + L.wtmp);
-    c->cls = (StumpDev*)(ws + L.cls);
-    c->scratch = L.total > L.scratch && sort_scratch_bytes(n) ? (uint64_t*)(ws + L.scratch) : nullptr;
-
-    std::vector<uint32_t> ftab((size_t)c->F);
-    host_feature_table(fs, ftab.data());
-    const uint32_t pd = pad_dword(jd.g);
-    const uint32_t pad_unit[4] = {pd, pd, pd, pd};
-    if (hipMemcpyAsync((void*)jd.ftab, ftab.data(), ftab.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemcpyAsync((void*)jd.pad, pad_unit, 16, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemsetAsync(jd.st, 0, sizeof(JobState), c->stream) != hipSuccess) {
-        set_error("copying the feature table failed");
-        return fail(BOOST_E_DEVICE);
-    }
-    if ((rc = ingest_launch(jd, d_labels, n, c->stream)) != BOOST_OK) return fail(rc);
-    JobState st;
-    if ((rc = sync_and_state(c, st)) != BOOST_OK) return fail(rc);
-    if (st.label_error) { set_error("labels must be 0 or 1"); return fail(BOOST_E_INVALID); }
-    if (st.n_pos == 0 || st.n_pos == n) {
-        set_error("both classes need at least one window (1/(2l) and 1/(2m) must exist)");
-        return fail(BOOST_E_INVALID);
-    }
-    if ((rc = integral_launch(jd, d_images, c->stream)) != BOOST_OK) return fail(rc);
-    if ((rc = sort_launch(jd, c->scratch, c->num_cu, c->stream)) != BOOST_OK) return fail(rc);
-    if ((rc = init_weights_launch(jd, c->stream)) != BOOST_OK) return fail(rc);
-    if ((rc = scan_plan(c->plan, o->precision, jd.g.narrow != 0, o->schedule_id, n, c->F, c->num_cu)) != BOOST_OK)
+    JobHost h;
+    if ((rc = setup_job(h, (char*)d_workspace, n, fs, o, d_images, d_labels, c->num_cu, c->stream)) != BOOST_OK)
+        return fail(rc);
+    c->jd = h.jd;
+    c->wtmp = h.wtmp;
+    c->cls = h.cls;
+    c->scratch = h.scratch;
+    if ((rc = scan_plan(c->plan, o->precision, c->jd.g.narrow != 0, o->schedule_id, n, c->F, c->num_cu)) != BOOST_OK)
         return fail(rc);
     if (hipStreamSynchronize(c->stream) != hipSuccess) { set_error("device error during init"); return fail(BOOST_E_DEVICE); }
     *out = c;

@@ -10,6 +10,8 @@ constexpr int kMaxSortGrid = 1024;   // upper bound of sort workgroups (fallback
 constexpr int kMaxPart = (int)((kMaxN + kUpdWg - 1) / kUpdWg);   // update workgroups of the largest job (<= 128)
 static_assert(kMaxPart <= 128, "weight_sum reads at most 128 partials");
 
+struct StumpDev { uint32_t desc; int32_t polarity; int32_t theta; int32_t pad; double alpha; };
+
 struct ScanPlan {
     const void* kernel = nullptr;
     int wg = 0;
@@ -17,10 +19,18 @@ struct ScanPlan {
     size_t lds = 0;
 };
 
+// api.cpp: one job's layout and one-time preparation (shared by the batch)
+struct JobHost { JobDev jd; double* wtmp; StumpDev* cls; uint64_t* scratch; };
+int check_job_args(int64_t n, const boost_feature_set* fs, const boost_options* o);
+size_t job_bytes(int64_t n, const boost_feature_set* fs);
+int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, const boost_options* o,
+              const uint8_t* d_images, const uint8_t* d_labels, int num_cu, hipStream_t s);
+
 // k_scan.hip
 int scan_schedule_count();
 int scan_schedule_wg(int schedule);
 int scan_schedule_lanes(int schedule);
+int scan_schedule_unroll(int schedule);
 int64_t scan_table_capacity(int precision, bool narrow);
 int scan_plan(ScanPlan& p, int precision, bool narrow, int schedule, int64_t n, int64_t F, int num_cu);
 int scan_launch(const ScanPlan& p, const JobDev& jd, double2* ferr, hipStream_t s);
@@ -35,7 +45,6 @@ int get_weights_launch(const JobDev& jd, double* d_out, hipStream_t s);
 int feature_values_launch(const JobDev& jd, int64_t j0, int64_t nf, int32_t* d_out, hipStream_t s);
 int integral_out_launch(const JobDev& jd, int32_t* d_out, hipStream_t s);
 int sorted_out_launch(const JobDev& jd, int64_t j0, int64_t nf, int32_t* d_order, uint8_t* d_flags, hipStream_t s);
-struct StumpDev { uint32_t desc; int32_t polarity; int32_t theta; int32_t pad; double alpha; };
 int classify_launch(const JobDev& jd, const StumpDev* d_stumps, int T, uint8_t* d_out, double* d_score, hipStream_t s);
 
 // k_sort.hip

@@ -396,3 +396,66 @@ class Trainer:
             self.close()
         except Exception:
             pass
+
+
+class BatchTrainer:
+    """Owns a batch of independent jobs advanced together (one scan launch and
+    one update launch per round for all jobs)."""
+
+    def __init__(self, datasets, type_mask: int = BOOST_ALL_TYPES, precision="fp32_wide",
+                 on_perfect: int = BOOST_ON_PERFECT_CLAMP, eps_floor: float = 1e-10,
+                 schedule_id: int = 0, flags: int = 0, device: str = "cuda:0"):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.inputs = []
+        arr = (Job * len(datasets))()
+        self.sizes = []
+        for k, (images, labels) in enumerate(datasets):
+            img = torch.as_tensor(images).to(self.device).contiguous()
+            lab = torch.as_tensor(labels).to(self.device).contiguous()
+            if img.dtype != torch.uint8 or lab.dtype != torch.uint8 or img.dim() != 3:
+                raise ValueError("images must be uint8 [N, H, W] and labels uint8 [N]")
+            n, h, w = (int(v) for v in img.shape)
+            self.inputs.append((img, lab))
+            self.sizes.append((n, h, w))
+            arr[k] = Job(img.data_ptr(), lab.data_ptr(), n, feature_set(w, h, type_mask))
+        self.jobs = arr
+        self.n_jobs = len(datasets)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.opts = options(precision, on_perfect, eps_floor, schedule_id, flags, self.stream.cuda_stream)
+        self.ws_bytes = boost_batch_workspace_bytes(arr, self.opts)
+        if self.ws_bytes == 0:
+            raise BoostError(BOOST_E_INVALID, last_error())
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self.ctx = boost_batch_init(arr, self.opts, self.workspace, self.ws_bytes)
+
+    def sync(self):
+        self.stream.synchronize()
+
+    def round(self):
+        return boost_batch_round(self.ctx, self.n_jobs, True)
+
+    def train(self, rounds: int, want_records: bool = True):
+        return boost_batch_train(self.ctx, rounds, self.n_jobs, want_records)
+
+    def weights(self, job: int):
+        torch = _torch()
+        w = torch.empty(self.sizes[job][0], dtype=torch.float64, device=self.device)
+        boost_batch_get_weights(self.ctx, job, w)
+        self.sync()
+        return w
+
+    def timing(self):
+        return boost_batch_get_timing(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            boost_batch_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
