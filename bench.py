@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "ms per boosting round (162k Haar × 15k imgs); batched jobs·rounds/s vs plain"
 SCAN_SOURCES = ["paper_1306_1467_amd/csrc/k_scan.hip", "paper_1306_1467_amd/csrc/scan_core.h",
-                "paper_1306_1467_amd/csrc/common.h"]
+                "paper_1306_1467_amd/csrc/round_core.h", "paper_1306_1467_amd/csrc/common.h"]
 
 
 def scan_source_hash() -> str:
@@ -154,7 +154,8 @@ def run_batched(config, args, torch, vb, synth):
     t_plain = 0.0
     plain = []
     for images, labels in data:
-        tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=prec, schedule_id=args.schedule)
+        tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=prec,
+                        schedule_id=args.batch_schedule)
         vb.boost_train(tr.ctx, 1, False)
         tr.stream.synchronize()
         t0 = time.perf_counter()
@@ -165,7 +166,7 @@ def run_batched(config, args, torch, vb, synth):
         torch.cuda.empty_cache()
     t0 = time.perf_counter()
     bt = vb.BatchTrainer([(torch.from_numpy(i), torch.from_numpy(l)) for i, l in data], precision=prec,
-                         schedule_id=args.schedule)
+                         schedule_id=args.batch_schedule)
     bt.sync()
     init_s = time.perf_counter() - t0
     bt.train(1, False)
@@ -174,6 +175,7 @@ def run_batched(config, args, torch, vb, synth):
     recs = bt.train(rounds, True)
     t_batch = time.perf_counter() - t0
     same = all(recs[:, k].tobytes() == plain[k].tobytes() for k in range(len(data)))
+    chosen = bt.schedule()
     keys = sum(vb.boost_feature_count(vb.feature_set(s.size)) * s.n for s in specs)
     jr = len(data) * rounds
     bt.close()
@@ -188,6 +190,9 @@ def run_batched(config, args, torch, vb, synth):
             "batched_ms_per_round": round(t_batch * 1e3 / rounds, 3),
             "batched_key_GBps": round(keys * 2 * rounds / t_batch / 1e9, 1),
             "batched_init_s": round(init_s, 2),
+            "schedule": {"requested": args.batch_schedule,
+                         "key14": {"schedule": chosen[0][0], "segs_per_wg": chosen[0][1]},
+                         "key15": {"schedule": chosen[1][0], "segs_per_wg": chosen[1][1]}},
             "stumps_identical_to_plain": bool(same)}
 
 
@@ -205,6 +210,8 @@ def main():
                     help="comma list of batched workloads to measure (3: 32 jobs, 4: 64 jobs); empty for none")
     ap.add_argument("--batch-rounds", type=int, default=0, help="rounds per batched job (0: the workload's own)")
     ap.add_argument("--batch-precision", default="fp32_wide")
+    ap.add_argument("--batch-schedule", type=int, default=-1,
+                    help="schedule of the batched and the plain per-job runs (-1: measured choice at init)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run one device copy of this many GiB first (counter calibration)")
     args = ap.parse_args()

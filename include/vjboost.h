@@ -89,8 +89,13 @@ typedef struct {
  *   the stump, leaves the weights unchanged and makes every later round a
  *   no-op (its record has feature = -1), returning BOOST_E_DEGENERATE.
  * eps_floor: > 0 and < 0.5 (default 1e-10).
- * schedule_id: 0 picks the default launch shape; 1.. select tuned variants
- *   (see boost_schedule_count).
+ * schedule_id: 0 picks the default launch shape (512-thread workgroups, 8
+ *   key units per load batch, 16 lanes per feature); 1 .. count-1 select
+ *   other shapes (see boost_schedule_count); BOOST_SCHEDULE_AUTO lets init
+ *   time every shape that shares the default's 16-lane key layout on the
+ *   job's own keys and keep the fastest (batches: per key format, then also
+ *   the work-queue granularity).  Choices are cached per process by workload
+ *   shape; boost_get_schedule / boost_batch_get_schedule report them.
  * flags: BOOST_FLAG_TIMING records per-kernel device times (boost_get_timing);
  *   BOOST_FLAG_NO_GRAPH launches kernels directly instead of replaying a
  *   captured HIP graph in boost_train. */
@@ -101,6 +106,8 @@ typedef struct {
 
 #define BOOST_ON_PERFECT_CLAMP 0
 #define BOOST_ON_PERFECT_STOP  1
+
+#define BOOST_SCHEDULE_AUTO (-1)
 
 #define BOOST_FLAG_TIMING   1
 #define BOOST_FLAG_NO_GRAPH 2
@@ -160,6 +167,9 @@ size_t boost_workspace_bytes(int64_t n, const boost_feature_set *fs, const boost
 /* Number of launch schedules (schedule_id values 0 .. count-1) for a precision. */
 int boost_schedule_count(int32_t precision);
 
+/* Forgets every BOOST_SCHEDULE_AUTO choice cached in this process. */
+void boost_tune_cache_clear(void);
+
 /* ------------------------------------------------------------ training
  * boost_init: ingest n windows and prepare every feature once (Section 3.3.1's
  * one-time "upload" of the feature values): copy labels and a positives-first
@@ -214,6 +224,13 @@ int boost_rounds_done(boost_ctx *c, int32_t *out_rounds);
 int boost_get_timing(boost_ctx *c, double out[4]);
 int boost_reset_timing(boost_ctx *c);
 
+/* Launch schedule in use (the tuner's choice under BOOST_SCHEDULE_AUTO).
+ * ms_out NULL or host double[cap]: ms_out[k] = the fastest of the timed scan
+ * launches of schedule k during tuning, -1 where schedule k was not timed
+ * (not a candidate, a fixed schedule, or a choice taken from the cache).
+ * Returns the schedule id, or BOOST_E_INVALID for a NULL context. */
+int boost_get_schedule(const boost_ctx *c, double *ms_out, int32_t cap);
+
 /* ------------------------------------------------------------ inspection (parity checks)
  * Values of features j0 .. j0+nf-1 on every window: device int32[nf][n],
  * caller's order (Section 2.2). */
@@ -241,9 +258,12 @@ void boost_destroy(boost_ctx *c);
 
 /* ------------------------------------------------------------ batched jobs
  * Many independent training jobs (each its own windows, labels and feature
- * set) advanced one round at a time by a single persistent scan launch plus
- * one finalize launch for all jobs.  Each job's results equal those of the
- * same job run alone through boost_init/boost_round with the same options. */
+ * set) advanced one round at a time: one persistent scan launch per key
+ * format present (jobs of at most 16,383 windows use 14-bit keys, larger ones
+ * 15-bit keys), whose workgroups take (job, feature range) segments from a
+ * work queue, then one update launch for all jobs.  Each job's results equal
+ * those of the same job run alone through boost_init/boost_round with the
+ * same options. */
 typedef struct {
     const uint8_t    *d_images;
     const uint8_t    *d_labels;
@@ -269,6 +289,13 @@ int boost_batch_train(boost_batch *b, int32_t rounds, boost_stump *out_host);
 
 /* Weights of job k, device double[n_k], caller's order. */
 int boost_batch_get_weights(boost_batch *b, int32_t job, double *d_w);
+
+/* Schedule of the scan launch for key format key_format (0: 14-bit keys,
+ * 1: 15-bit keys): *schedule = its schedule id, or -1 when no job of the
+ * batch uses that format; *segs_per_wg (if not NULL) = work-queue segments
+ * per workgroup (0 when absent).  BOOST_E_INVALID for a NULL batch or
+ * schedule pointer or a format other than 0 and 1. */
+int boost_batch_get_schedule(const boost_batch *b, int32_t key_format, int32_t *schedule, int32_t *segs_per_wg);
 
 /* As boost_get_timing, summed over the batch's launches. */
 int boost_batch_get_timing(boost_batch *b, double out[4]);

@@ -22,7 +22,8 @@ bool valid_options(const boost_options* o) {
     if (o->precision < BOOST_PREC_FP32 || o->precision > BOOST_PREC_FP32_WIDE) return false;
     if (o->on_perfect != BOOST_ON_PERFECT_CLAMP && o->on_perfect != BOOST_ON_PERFECT_STOP) return false;
     if (!(o->eps_floor > 0.0) || !(o->eps_floor < 0.5)) return false;
-    if (o->schedule_id < 0 || o->schedule_id >= scan_schedule_count()) return false;
+    if (o->schedule_id != BOOST_SCHEDULE_AUTO && (o->schedule_id < 0 || o->schedule_id >= scan_schedule_count()))
+        return false;
     if (o->flags & ~(BOOST_FLAG_TIMING | BOOST_FLAG_NO_GRAPH)) return false;
     return true;
 }
@@ -102,7 +103,7 @@ int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, cons
     jd.ring = (boost_stump*)(ws + L.ring);
     jd.perm = (const int32_t*)(ws + L.perm);
     jd.inv = (const int32_t*)(ws + L.inv);
-    jd.g = make_geom(n, scan_schedule_lanes(o->schedule_id));
+    jd.g = make_geom(n, scan_schedule_lanes(o->schedule_id < 0 ? 0 : o->schedule_id));
     jd.F = host_feature_count(fs);
     jd.ii_stride = ii_stride_of(n);
     jd.W = fs->window_w;
@@ -153,6 +154,8 @@ struct boost_ctx {
     boost_feature_set fs;
     int64_t n = 0, F = 0;
     ScanPlan plan;
+    int schedule = 0;
+    std::vector<double> tune_ms;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<hipEvent_t> ev;
@@ -188,6 +191,13 @@ int boost_feature_desc(const boost_feature_set* fs, int64_t j, boost_feature* ou
 int boost_schedule_count(int32_t precision) {
     (void)precision;
     return scan_schedule_count();
+}
+
+int boost_get_schedule(const boost_ctx* c, double* ms_out, int32_t cap) {
+    if (!c) { set_error("NULL context"); return BOOST_E_INVALID; }
+    if (ms_out)
+        for (int k = 0; k < cap && k < (int)c->tune_ms.size(); ++k) ms_out[k] = c->tune_ms[(size_t)k];
+    return c->schedule;
 }
 
 size_t boost_workspace_bytes(int64_t n, const boost_feature_set* fs, const boost_options* o) {
@@ -227,7 +237,13 @@ int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels
     c->wtmp = h.wtmp;
     c->cls = h.cls;
     c->scratch = h.scratch;
-    if ((rc = scan_plan(c->plan, o->precision, c->jd.g.narrow != 0, o->schedule_id, n, c->F, c->num_cu)) != BOOST_OK)
+    c->schedule = o->schedule_id;
+    c->tune_ms.assign((size_t)scan_schedule_count(), -1.0);
+    if (o->schedule_id == BOOST_SCHEDULE_AUTO &&
+        (rc = tune_single(c->jd, o->precision, c->num_cu, c->device, c->stream, c->tune_ms.data(), c->schedule)) !=
+            BOOST_OK)
+        return fail(rc);
+    if ((rc = scan_plan(c->plan, o->precision, c->jd.g.narrow != 0, c->schedule, n, c->F, c->num_cu)) != BOOST_OK)
         return fail(rc);
     if (hipStreamSynchronize(c->stream) != hipSuccess) { set_error("device error during init"); return fail(BOOST_E_DEVICE); }
     *out = c;

@@ -38,9 +38,9 @@ static void batch_layout(int32_t n_jobs, const boost_job* jobs, BatchLayout& L) 
         L.job_off.push_back(take(job_bytes(jobs[k].n, &jobs[k].fs)));
         L.n_upd += (jobs[k].n + kUpdWg - 1) / kUpdWg;
     }
-    // per launch at most about grid * kSegsPerWg (rounding of the segment
-    // length adds under 2 %) plus one per job
-    const size_t max_segs = (size_t)4 * kMaxScanGrid * kSegsPerWg + (size_t)n_jobs;
+    // per launch at most about grid * segments per workgroup (rounding of the
+    // segment length adds under 2 %) plus one per job
+    const size_t max_segs = (size_t)2 * 2 * kMaxScanGrid * kMaxSegsPerWg + (size_t)n_jobs;
     L.max_segs = max_segs;
     L.jobs = take((size_t)n_jobs * sizeof(JobDev));
     L.segs = take(max_segs * sizeof(BatchSeg));
@@ -53,31 +53,56 @@ static void batch_layout(int32_t n_jobs, const boost_job* jobs, BatchLayout& L) 
     L.total = off;
 }
 
+// Launch configuration of one key format's scan.
+struct PartCfg {
+    int schedule = -1, wg = 0, unroll = 0, spw = kSegsPerWg, grid = 0;
+    const void* kernel = nullptr;
+};
+
+static int part_config(PartCfg& pc, int precision, bool narrow, int schedule, int num_cu) {
+    pc.schedule = schedule;
+    pc.wg = scan_schedule_wg(schedule);
+    pc.unroll = scan_schedule_unroll(schedule);
+    pc.kernel = batch_scan_kernel(precision, narrow, schedule);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pc.kernel, pc.wg, 0) != hipSuccess || per_cu < 1) {
+        set_error("batched scan kernel does not fit on a compute unit");
+        return BOOST_E_INVALID;
+    }
+    int64_t grid = (int64_t)per_cu * num_cu;
+    if (grid > kMaxScanGrid) grid = kMaxScanGrid;
+    pc.grid = (int)grid;
+    return BOOST_OK;
+}
+
 // Cuts every job's features into segments of about the same cost for the
-// work queues: about grid * kSegsPerWg segments per launch.  A feature of job
-// k costs the key units its lanes walk (padding of the last batch included)
+// work queues: about grid * spw segments per launch.  A feature of job k
+// costs the key units its lanes walk (padding of the tail batch included)
 // plus about two units per lane for the group epilogue.  The 14-bit-key jobs'
 // segments come first (launch 0), then the 15-bit ones' (launch 1).
-static void build_segments(const std::vector<JobHost>& jobs, const int grid[2], int unroll,
-                           std::vector<BatchSeg>& segs, std::vector<int32_t>& job_seg, int32_t& split) {
+static void build_segments(const std::vector<JobHost>& jobs, const PartCfg part[2], std::vector<BatchSeg>& segs,
+                           std::vector<int32_t>& job_seg, int32_t& split) {
     const int n_jobs = (int)jobs.size();
     std::vector<double> cost(n_jobs);
     double total[2] = {0, 0};
     for (int k = 0; k < n_jobs; ++k) {
         const KeyGeom& g = jobs[k].jd.g;
-        const int64_t per_lane = g.q + (g.rem > 0 ? 1 : 0);
-        const int64_t nb = (per_lane + unroll - 1) / unroll;
-        cost[k] = (double)(nb * unroll + 2) * g.lanes;
-        total[g.narrow ? 0 : 1] += cost[k] * (double)jobs[k].jd.F;
+        const int pk = g.narrow ? 0 : 1;
+        const int64_t unroll = part[pk].unroll > 0 ? part[pk].unroll : 8;
+        const int64_t per = g.q + (g.rem > 0 ? 1 : 0), rest = per % unroll;
+        const int64_t walked =
+            per <= unroll ? unroll : per - rest + (rest == 0 ? 0 : rest <= unroll / 2 ? unroll / 2 : unroll);
+        cost[k] = (double)(walked + 2) * g.lanes;
+        total[pk] += cost[k] * (double)jobs[k].jd.F;
     }
     segs.clear();
     job_seg.assign((size_t)2 * n_jobs, 0);
-    for (int part = 0; part < 2; ++part) {
-        if (part == 1) split = (int32_t)segs.size();
-        if (grid[part] <= 0) continue;
-        const double target = total[part] / ((double)grid[part] * kSegsPerWg);
+    for (int pk = 0; pk < 2; ++pk) {
+        if (pk == 1) split = (int32_t)segs.size();
+        if (part[pk].grid <= 0) continue;
+        const double target = total[pk] / ((double)part[pk].grid * part[pk].spw);
         for (int k = 0; k < n_jobs; ++k) {
-            if ((jobs[k].jd.g.narrow ? 0 : 1) != part) continue;
+            if ((jobs[k].jd.g.narrow ? 0 : 1) != pk) continue;
             job_seg[2 * k] = (int32_t)segs.size();
             const int64_t F = jobs[k].jd.F;
             int64_t per = (int64_t)(target / cost[k]);
@@ -95,9 +120,10 @@ struct boost_batch {
     std::vector<JobHost> jobs;
     BatchDev bd;
     boost_stump* gather = nullptr;
-    int grid[2] = {0, 0}, wg = 0, num_cu = 0;
+    PartCfg part[2];
+    int num_cu = 0, device = 0;
+    size_t max_segs = 0;
     int64_t n_upd = 0;
-    const void* scan_kernel[2] = {nullptr, nullptr};
     hipStream_t stream = nullptr;
     boost_options opts;
     hipGraph_t graph = nullptr;
@@ -106,6 +132,77 @@ struct boost_batch {
     double t_scan = 0, t_upd = 0, rounds_timed = 0;
     int64_t launched = 0;
 };
+
+// Builds the segment tables for the current part configurations and copies
+// them to the device (stream-ordered).
+static int upload_segments(boost_batch* b) {
+    std::vector<BatchSeg> segs;
+    std::vector<int32_t> job_seg;
+    int32_t split = 0;
+    build_segments(b->jobs, b->part, segs, job_seg, split);
+    if (segs.size() > b->max_segs) { set_error("segment table overflow"); return BOOST_E_INVALID; }
+    b->bd.n_segs = (int32_t)segs.size();
+    b->bd.seg_split = split;
+    VJB_HIP(hipMemcpyAsync((void*)b->bd.segs, segs.data(), segs.size() * sizeof(BatchSeg), hipMemcpyHostToDevice,
+                           b->stream));
+    VJB_HIP(hipMemcpyAsync((void*)b->bd.job_seg, job_seg.data(), job_seg.size() * 4, hipMemcpyHostToDevice, b->stream));
+    VJB_HIP(hipStreamSynchronize(b->stream));   // the host vectors end here
+    return BOOST_OK;
+}
+
+static int launch_part(boost_batch* b, int p) {
+    return batch_scan_launch(b->part[p].kernel, b->part[p].grid, b->part[p].wg, b->bd, p, b->stream);
+}
+
+// Times one part's scan under its current configuration (the queue counter is
+// cleared before each launch; the other part is not launched).
+static int time_part(boost_batch* b, int p, double& ms) {
+    return time_launches(b->stream, kTuneReps, [&]() -> int {
+        VJB_HIP(hipMemsetAsync(b->bd.next_seg + p, 0, 4, b->stream));
+        return launch_part(b, p);
+    }, ms);
+}
+
+// Measured choice for one key format: first the schedule (with the default
+// segment granularity), then the segments per workgroup.
+static int tune_part(boost_batch* b, int p) {
+    std::string key = "batch/" + std::to_string(b->device) + "/" + std::to_string(b->opts.precision) + "/" +
+                      std::to_string(p);
+    for (const JobHost& h : b->jobs)
+        if ((h.jd.g.narrow ? 0 : 1) == p) key += "/" + std::to_string(h.jd.g.n) + "x" + std::to_string(h.jd.F);
+    std::vector<int> hit;
+    int rc;
+    if (tune_cache_get(key, hit)) {
+        if ((rc = part_config(b->part[p], b->opts.precision, p == 0, hit[0], b->num_cu)) != BOOST_OK) return rc;
+        b->part[p].spw = hit[1];
+        return upload_segments(b);
+    }
+    const int lanes = scan_schedule_lanes(b->part[p].schedule);
+    PartCfg best = b->part[p];
+    double best_ms = 1e300;
+    for (int k = 0; k < scan_schedule_count(); ++k) {
+        if (scan_schedule_lanes(k) != lanes) continue;
+        PartCfg pc;
+        if (part_config(pc, b->opts.precision, p == 0, k, b->num_cu) != BOOST_OK) continue;
+        b->part[p] = pc;
+        double ms = 0;
+        if ((rc = upload_segments(b)) != BOOST_OK || (rc = time_part(b, p, ms)) != BOOST_OK) return rc;
+        if (ms < best_ms) { best_ms = ms; best = pc; }
+    }
+    static const int kSpw[] = {2, 8, 16};
+    b->part[p] = best;
+    for (int spw : kSpw) {
+        PartCfg pc = best;
+        pc.spw = spw;
+        b->part[p] = pc;
+        double ms = 0;
+        if ((rc = upload_segments(b)) != BOOST_OK || (rc = time_part(b, p, ms)) != BOOST_OK) return rc;
+        if (ms < best_ms) { best_ms = ms; best = pc; }
+    }
+    b->part[p] = best;
+    tune_cache_put(key, {best.schedule, best.spw});
+    return upload_segments(b);
+}
 
 extern "C" {
 
@@ -141,6 +238,7 @@ int boost_batch_init(boost_batch** out, int32_t n_jobs, const boost_job* jobs, c
         set_error("no HIP device");
         return fail(BOOST_E_DEVICE);
     }
+    b->device = dev;
     char* ws = (char*)d_workspace;
     b->jobs.resize(n_jobs);
     for (int k = 0; k < n_jobs; ++k) {
@@ -148,53 +246,43 @@ int boost_batch_init(boost_batch** out, int32_t n_jobs, const boost_job* jobs, c
                        b->num_cu, b->stream);
         if (rc != BOOST_OK) { set_error("job " + std::to_string(k) + ": " + get_error()); return fail(rc); }
     }
-    // one scan launch per key format present
-    b->wg = scan_schedule_wg(o->schedule_id);
-    bool present[2] = {false, false};
-    for (int k = 0; k < n_jobs; ++k) present[b->jobs[k].jd.g.narrow ? 0 : 1] = true;
-    for (int part = 0; part < 2; ++part) {
-        if (!present[part]) continue;
-        b->scan_kernel[part] = batch_scan_kernel(o->precision, part == 0, o->schedule_id);
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, b->scan_kernel[part], b->wg, 0) != hipSuccess ||
-            per_cu < 1) {
-            set_error("batched scan kernel does not fit on a compute unit");
-            return fail(BOOST_E_INVALID);
-        }
-        int64_t grid = (int64_t)per_cu * b->num_cu;
-        if (grid > kMaxScanGrid) grid = kMaxScanGrid;
-        b->grid[part] = (int)grid;
-    }
     // device tables
     std::vector<JobDev> hj(n_jobs);
     for (int k = 0; k < n_jobs; ++k) hj[k] = b->jobs[k].jd;
-    std::vector<BatchSeg> segs;
-    std::vector<int32_t> job_seg, upd_job, upd_part;
-    int32_t split = 0;
-    build_segments(b->jobs, b->grid, scan_schedule_unroll(o->schedule_id), segs, job_seg, split);
-    if (segs.size() > L.max_segs) { set_error("segment table overflow"); return fail(BOOST_E_INVALID); }
+    std::vector<int32_t> upd_job, upd_part;
     for (int k = 0; k < n_jobs; ++k)
         for (int p = 0; p < b->jobs[k].jd.n_part; ++p) { upd_job.push_back(k); upd_part.push_back(p); }
     b->n_upd = (int64_t)upd_job.size();
+    b->max_segs = L.max_segs;
     BatchDev& bd = b->bd;
     bd.jobs = (const JobDev*)(ws + L.jobs);
     bd.segs = (const BatchSeg*)(ws + L.segs);
     bd.next_seg = (uint32_t*)(ws + L.next_seg);
-    bd.n_segs = (int32_t)segs.size();
-    bd.seg_split = split;
     bd.job_seg = (const int32_t*)(ws + L.job_seg);
     bd.seg_best = (WgBest*)(ws + L.seg_best);
     bd.upd_job = (const int32_t*)(ws + L.upd_job);
     bd.upd_part = (const int32_t*)(ws + L.upd_part);
     b->gather = (boost_stump*)(ws + L.gather);
     if (hipMemcpyAsync((void*)bd.jobs, hj.data(), hj.size() * sizeof(JobDev), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipMemcpyAsync((void*)bd.segs, segs.data(), segs.size() * sizeof(BatchSeg), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipMemsetAsync(bd.next_seg, 0, 8, b->stream) != hipSuccess ||
-        hipMemcpyAsync((void*)bd.job_seg, job_seg.data(), job_seg.size() * 4, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipMemcpyAsync((void*)bd.upd_job, upd_job.data(), upd_job.size() * 4, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipMemcpyAsync((void*)bd.upd_part, upd_part.data(), upd_part.size() * 4, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipStreamSynchronize(b->stream) != hipSuccess) {
+        hipMemcpyAsync((void*)bd.upd_part, upd_part.data(), upd_part.size() * 4, hipMemcpyHostToDevice, b->stream) != hipSuccess) {
         set_error("copying the batch tables failed");
+        return fail(BOOST_E_DEVICE);
+    }
+    // one scan launch per key format present, with its schedule
+    bool present[2] = {false, false};
+    for (int k = 0; k < n_jobs; ++k) present[b->jobs[k].jd.g.narrow ? 0 : 1] = true;
+    const int sched0 = o->schedule_id == BOOST_SCHEDULE_AUTO ? 0 : o->schedule_id;
+    for (int p = 0; p < 2; ++p)
+        if (present[p] && (rc = part_config(b->part[p], o->precision, p == 0, sched0, b->num_cu)) != BOOST_OK)
+            return fail(rc);
+    if ((rc = upload_segments(b)) != BOOST_OK) return fail(rc);
+    if (o->schedule_id == BOOST_SCHEDULE_AUTO)
+        for (int p = 0; p < 2; ++p)
+            if (present[p] && (rc = tune_part(b, p)) != BOOST_OK) return fail(rc);
+    if (hipMemsetAsync(bd.next_seg, 0, 8, b->stream) != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess) {
+        set_error("device error during batch init");
         return fail(BOOST_E_DEVICE);
     }
     *out = b;
@@ -204,10 +292,8 @@ int boost_batch_init(boost_batch** out, int32_t n_jobs, const boost_job* jobs, c
 static int batch_launch(boost_batch* b, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
     int rc;
     if (e0) VJB_HIP(hipEventRecord(e0, b->stream));
-    for (int part = 0; part < 2; ++part)
-        if (b->scan_kernel[part] &&
-            (rc = batch_scan_launch(b->scan_kernel[part], b->grid[part], b->wg, b->bd, part, b->stream)) != BOOST_OK)
-            return rc;
+    for (int p = 0; p < 2; ++p)
+        if (b->part[p].kernel && (rc = launch_part(b, p)) != BOOST_OK) return rc;
     if (e1) VJB_HIP(hipEventRecord(e1, b->stream));
     if ((rc = batch_update_launch(b->opts.precision, (int)b->n_upd, b->bd, b->stream)) != BOOST_OK) return rc;
     if (e2) VJB_HIP(hipEventRecord(e2, b->stream));
@@ -219,8 +305,8 @@ static int batch_graph(boost_batch* b) {
     if (b->gexec) return BOOST_OK;
     VJB_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     int rc = BOOST_OK;
-    for (int part = 0; part < 2 && rc == BOOST_OK; ++part)
-        if (b->scan_kernel[part]) rc = batch_scan_launch(b->scan_kernel[part], b->grid[part], b->wg, b->bd, part, b->stream);
+    for (int p = 0; p < 2 && rc == BOOST_OK; ++p)
+        if (b->part[p].kernel) rc = launch_part(b, p);
     if (rc == BOOST_OK) rc = batch_update_launch(b->opts.precision, (int)b->n_upd, b->bd, b->stream);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->stream, &g);
@@ -288,6 +374,17 @@ int boost_batch_round(boost_batch* b, boost_stump* out_host) { return boost_batc
 int boost_batch_get_weights(boost_batch* b, int32_t job, double* d_w) {
     if (!b || !d_w || job < 0 || job >= b->n_jobs) { set_error("invalid batch, job or output"); return BOOST_E_INVALID; }
     return get_weights_launch(b->jobs[job].jd, d_w, b->stream);
+}
+
+int boost_batch_get_schedule(const boost_batch* b, int32_t key_format, int32_t* schedule, int32_t* segs_per_wg) {
+    if (!b || !schedule || key_format < 0 || key_format > 1) {
+        set_error("invalid batch, key format or output");
+        return BOOST_E_INVALID;
+    }
+    const PartCfg& pc = b->part[key_format];
+    *schedule = pc.kernel ? pc.schedule : -1;
+    if (segs_per_wg) *segs_per_wg = pc.kernel ? pc.spw : 0;
+    return BOOST_OK;
 }
 
 int boost_batch_get_timing(boost_batch* b, double out[4]) {

@@ -1,6 +1,10 @@
 // Host launchers of the library's kernels (one translation unit per kernel family).
 #pragma once
 
+#include <functional>
+#include <string>
+#include <vector>
+
 #include "common.h"
 
 namespace vjb {
@@ -35,6 +39,15 @@ int64_t scan_table_capacity(int precision, bool narrow);
 int scan_plan(ScanPlan& p, int precision, bool narrow, int schedule, int64_t n, int64_t F, int num_cu);
 int scan_launch(const ScanPlan& p, const JobDev& jd, double2* ferr, hipStream_t s);
 int update_launch(const JobDev& jd, int n_wg, hipStream_t s);
+
+// tune.cpp: measured schedule choice
+constexpr int kTuneReps = 3;   // timed launches per candidate (the minimum counts)
+int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, double& best_ms);
+bool tune_cache_get(const std::string& key, std::vector<int>& choice);
+void tune_cache_put(const std::string& key, const std::vector<int>& choice);
+// Times every schedule with the job's lane count; ms_out[k] = -1 for schedules
+// not tried (or when the choice came from the cache).
+int tune_single(const JobDev& jd, int precision, int num_cu, int device, hipStream_t s, double* ms_out, int& chosen);
 
 // k_prep.hip
 int ingest_launch(const JobDev& jd, const uint8_t* d_labels, int64_t n, hipStream_t s);

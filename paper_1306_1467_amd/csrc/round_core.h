@@ -49,10 +49,20 @@ __device__ __forceinline__ WgBest scan_range(const JobDev& jd, const typename Sc
                                              int64_t f1, int64_t step0, int64_t nsteps, double tp, double tn,
                                              double2* __restrict__ ferr) {
     constexpr int G = 64 / LPF;
+    constexpr int H = UNROLL / 2;
+    static_assert(UNROLL % 2 == 0, "the tail batch is half a batch");
     const int lane = threadIdx.x & 63;
     const int grp = lane / LPF, L = lane % LPF;
     const int cnt = jd.g.q + (L < jd.g.rem ? 1 : 0);
-    const int nb = (jd.g.q + (jd.g.rem > 0 ? 1 : 0) + UNROLL - 1) / UNROLL;
+    // Units per lane (the longest lane) = nbf full batches, then a half batch
+    // when at most UNROLL / 2 units remain (and at least one full batch came
+    // before).  Only the last batch can reach past a lane's own units (into
+    // the padding unit).
+    const int per = jd.g.q + (jd.g.rem > 0 ? 1 : 0);
+    const int rest = per % UNROLL;
+    const bool half = rest > 0 && rest <= H && per > UNROLL;
+    const int nbf = per / UNROLL + (rest > 0 && !half ? 1 : 0);
+    const int nb = nbf + (half ? 1 : 0);
     WgBest best{DBL_MAX, -1, 0, -1};
     // features past f1 read the padding unit (stride 0) and are dropped
     auto row_of = [&](int64_t j, int& stride) -> const uint4* {
@@ -73,10 +83,15 @@ __device__ __forceinline__ WgBest scan_range(const JobDev& jd, const typename Sc
         LaneAcc<PREC> a;
 #pragma unroll
         for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
-        for (int b = 1; b < nb; ++b) {
+        for (int b = 1; b < nbf; ++b) {
             load_batch<UNROLL>(u, p, stride, b, nb, stride ? cnt : 0, jd.pad);
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
+        }
+        if (half) {
+            load_tail<H>(u, p, stride, nbf * UNROLL, stride ? cnt : 0, jd.pad);
+#pragma unroll
+            for (int k = 0; k < H; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
         }
         const int64_t jcur = j;
         t += nsteps;

@@ -253,6 +253,17 @@ __device__ __forceinline__ void load_batch(uint4* u, const uint4* __restrict__ p
     }
 }
 
+// H units from unit `start` on; units at or past cnt read the padding unit.
+template <int H>
+__device__ __forceinline__ void load_tail(uint4* u, const uint4* __restrict__ p, int stride, int start, int cnt,
+                                          const uint4* __restrict__ pad) {
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const int r = start + k;
+        u[k] = ld_stream(r < cnt ? p + stride * r : pad);
+    }
+}
+
 // Group-level end of one feature's scan: lane totals -> exclusive prefix ->
 // extremes of the running sum at run ends -> errors for both polarities.
 template <int PREC, int LPF>

@@ -32,6 +32,7 @@ BOOST_ON_PERFECT_CLAMP = 0
 BOOST_ON_PERFECT_STOP = 1
 BOOST_FLAG_TIMING = 1
 BOOST_FLAG_NO_GRAPH = 2
+BOOST_SCHEDULE_AUTO = -1
 BOOST_ALL_TYPES = 0x1F
 
 
@@ -82,6 +83,8 @@ _SIGS = {
     "boost_feature_desc": (ctypes.c_int, [ctypes.POINTER(FeatureSet), ctypes.c_int64, ctypes.POINTER(Feature)]),
     "boost_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.POINTER(FeatureSet), ctypes.POINTER(Options)]),
     "boost_schedule_count": (ctypes.c_int, [ctypes.c_int32]),
+    "boost_tune_cache_clear": (None, []),
+    "boost_get_schedule": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "boost_init": (ctypes.c_int, [ctypes.POINTER(_P), _P, _P, ctypes.c_int64, ctypes.POINTER(FeatureSet),
                                   ctypes.POINTER(Options), _P, ctypes.c_size_t]),
     "boost_round": (ctypes.c_int, [_P, ctypes.POINTER(Stump), _P]),
@@ -103,6 +106,8 @@ _SIGS = {
     "boost_batch_train": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "boost_batch_get_weights": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "boost_batch_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "boost_batch_get_schedule": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                                ctypes.POINTER(ctypes.c_int32)]),
     "boost_batch_destroy": (None, [_P]),
 }
 
@@ -226,6 +231,19 @@ def boost_reset_timing(ctx):
     _check(lib().boost_reset_timing(ctx))
 
 
+def boost_get_schedule(ctx):
+    """(schedule in use, per-schedule tuning times in ms or -1 where not timed)."""
+    cap = boost_schedule_count()
+    ms = (ctypes.c_double * cap)()
+    rc = lib().boost_get_schedule(ctx, ctypes.cast(ms, _P), cap)
+    _check(min(rc, 0))
+    return int(rc), list(ms)
+
+
+def boost_tune_cache_clear():
+    lib().boost_tune_cache_clear()
+
+
 def boost_get_feature_values(ctx, j0: int, nf: int, d_out):
     _check(lib().boost_get_feature_values(ctx, j0, nf, _ptr(d_out)))
 
@@ -281,6 +299,15 @@ def boost_batch_get_timing(b):
     out = (ctypes.c_double * 4)()
     _check(lib().boost_batch_get_timing(b, out))
     return list(out)
+
+
+def boost_batch_get_schedule(b, key_format: int):
+    """(schedule id or -1 when absent, segments per workgroup) of the scan
+    launch for key format 0 (14-bit keys) or 1 (15-bit keys)."""
+    sched = ctypes.c_int32(0)
+    spw = ctypes.c_int32(0)
+    _check(lib().boost_batch_get_schedule(b, key_format, ctypes.byref(sched), ctypes.byref(spw)))
+    return int(sched.value), int(spw.value)
 
 
 def boost_batch_destroy(b):
@@ -386,6 +413,9 @@ class Trainer:
     def rounds_done(self):
         return boost_rounds_done(self.ctx)
 
+    def schedule(self):
+        return boost_get_schedule(self.ctx)
+
     def close(self):
         if getattr(self, "ctx", None) is not None:
             boost_destroy(self.ctx)
@@ -448,6 +478,9 @@ class BatchTrainer:
 
     def timing(self):
         return boost_batch_get_timing(self.ctx)
+
+    def schedule(self):
+        return [boost_batch_get_schedule(self.ctx, k) for k in (0, 1)]
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

@@ -79,6 +79,18 @@ def test_workspace_bytes_validation(vb):
     bad = vb.options()
     bad.schedule_id = vb.boost_schedule_count()
     assert vb.boost_workspace_bytes(100, fs, bad) == 0
+    bad.schedule_id = -2
+    assert vb.boost_workspace_bytes(100, fs, bad) == 0
+    auto = vb.options(schedule_id=vb.BOOST_SCHEDULE_AUTO)
+    assert vb.boost_workspace_bytes(100, fs, auto) == vb.boost_workspace_bytes(100, fs, o)
+
+
+def test_schedule_queries_reject_null(vb):
+    L = vb.lib()
+    s = ctypes.c_int32(0)
+    assert L.boost_get_schedule(None, None, 0) == vb.BOOST_E_INVALID
+    assert L.boost_batch_get_schedule(None, 0, ctypes.byref(s), None) == vb.BOOST_E_INVALID
+    L.boost_tune_cache_clear()
 
 
 def test_init_rejects_bad_arguments_before_device_work(vb):
