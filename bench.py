@@ -16,7 +16,6 @@ host cores for a bounded sample of features.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -27,28 +26,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "ms per boosting round (162k Haar × 15k imgs); batched jobs·rounds/s vs plain"
-SCAN_SOURCES = ["paper_1306_1467_amd/csrc/k_scan.hip", "paper_1306_1467_amd/csrc/scan_core.h",
-                "paper_1306_1467_amd/csrc/round_core.h", "paper_1306_1467_amd/csrc/common.h"]
-
-
-def scan_source_hash() -> str:
-    h = hashlib.sha256()
-    for p in SCAN_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
-def profiled_traffic(kind: str, precision: str):
+def profiled_traffic(kind: str, precision: str, schedule: int):
     """HBM bytes per scan launch from the committed rocprofv3 counter summary,
-    or None when it is missing or was taken on a different scan source."""
+    or None when it is missing or was taken on a different scan source,
+    precision or schedule."""
+    from paper_1306_1467_amd.profsum import scan_source_hash
     path = os.path.join(ROOT, "profiles", f"stump_scan_{kind}_counters.json")
     try:
         with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("scan_source_hash") != scan_source_hash() or d.get("precision") != precision:
+    if (d.get("scan_source_hash") != scan_source_hash() or d.get("precision") != precision
+            or d.get("schedule") != schedule):
         return None
     return d.get("bytes_per_launch")
 
@@ -122,7 +112,7 @@ def run_single(args, torch, vb, synth):
     scan_avg = scan_ms / nr
     alg_bytes = F * n * 2
     achieved = alg_bytes / (scan_avg * 1e-3) / 1e9
-    traffic = profiled_traffic("config1", args.precision)
+    traffic = profiled_traffic("config1", args.precision, args.schedule)
     out = {
         "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
         "graph_event_ms_per_round": round(graph_ms, 4),
@@ -132,7 +122,9 @@ def run_single(args, torch, vb, synth):
         "update_ms_avg": round(upd_ms / nr, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if traffic is None else round(traffic / (scan_avg * 1e-3) / 1e9, 1),
+                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                                         "copy-calibrated)",
+                     "traffic_GBps": None if traffic is None else round(traffic / (scan_avg * 1e-3) / 1e9, 1),
                      "kernel": "k_scan", "alg_bytes_per_launch": alg_bytes},
         "last_round": {"feature": int(rec.feature), "error_raw": rec.error_raw, "polarity": int(rec.polarity),
                        "threshold": int(rec.threshold)},

@@ -74,8 +74,8 @@ typedef struct {
  * precision: arithmetic of the per-round weighted-error scan.
  *   BOOST_PREC_FP32        FP32 weights, FP32 running sums (plain).
  *   BOOST_PREC_FP32_KAHAN  FP32 weights, FP32 running sums with two-sum
- *                          compensation; candidates compared on the
- *                          compensated FP32 prefix.
+ *                          compensation; candidates (the compensated
+ *                          prefix s + c) are compared in FP64.
  *   BOOST_PREC_FP64        FP64 weights and FP64 running sums (n <= 20000:
  *                          the table must fit in LDS).
  *   BOOST_PREC_FP32_WIDE   FP32 weights accumulated in FP64.  For weights

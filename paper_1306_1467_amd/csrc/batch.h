@@ -26,7 +26,7 @@ struct BatchDev {
 
 constexpr int kGatherRounds = 256;   // records gathered per copy
 constexpr int kSegsPerWg = 4;        // work-queue granularity: segments per scan workgroup on average
-constexpr int kMaxSegsPerWg = 16;    // the largest granularity the tuner tries
+constexpr int kMaxSegsPerWg = 32;    // the largest granularity the tuner tries
 constexpr int kMaxJobs = 4096;
 
 const void* batch_scan_kernel(int precision, bool narrow, int schedule);
