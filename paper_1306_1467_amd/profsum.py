@@ -2,6 +2,10 @@
 
   python -m paper_1306_1467_amd.profsum stats <kernel_stats.csv> --command "..." [--title T]
       prints a markdown table of per-kernel device times.
+  python -m paper_1306_1467_amd.profsum activity <counter.csv> [<counter.csv> ...] --kernel REGEX
+      --keys K --commands "..." [...]
+      prints per-launch SQ/GRBM counters of the matching kernel and derived
+      unit activity (VALU and LDS issue per key, busy fractions).
   python -m paper_1306_1467_amd.profsum counters <fetch.csv> <write.csv> --copy-gib G
       --kernel REGEX --precision P --schedule S --command-fetch "..." --command-write "..." --json OUT
       prints a markdown summary of HBM traffic per launch of the matching kernel
@@ -102,6 +106,36 @@ def counters(fetch_csv: str, write_csv: str, copy_gib: float, kernel: str, preci
     return "\n".join(lines) + "\n"
 
 
+def activity(paths, kernel: str, keys: int, commands, cus: int = 256, simds_per_cu: int = 4, xcds: int = 8) -> str:
+    pat = re.compile(kernel)
+    agg = {}
+    for path in paths:
+        for r in _dispatches(path):
+            if pat.search(r["Kernel_Name"]):
+                agg.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    m = {k: statistics.mean(v) for k, v in agg.items()}
+    lines = [f"# Unit activity of `{kernel}` (rocprofv3 counters, mean per launch)", ""]
+    for c in commands:
+        lines += ["```", c, "```", ""]
+    lines += ["| counter | mean per launch | launches |", "|---|---:|---:|"]
+    for k in sorted(agg):
+        lines.append(f"| {k} | {m[k]:,.0f} | {len(agg[k])} |")
+    lines.append("")
+    slots = keys / 64.0   # wave-wide key slots
+    if "GRBM_GUI_ACTIVE" in m:
+        cyc = m["GRBM_GUI_ACTIVE"] / xcds   # GRBM_GUI_ACTIVE is summed over the XCDs
+        lines.append(f"- GPU-busy cycles per XCD: {cyc:,.0f}")
+        if "SQ_INSTS_VALU" in m:
+            lines.append(f"- VALU instructions per key (wave-wide): {m['SQ_INSTS_VALU'] / slots:.2f}")
+            busy = m["SQ_INSTS_VALU"] * 4.0 / (cus * simds_per_cu) / cyc
+            lines.append(f"- VALU issue (4 cycles per wave64 instruction) per SIMD / busy cycles: {busy:.2f}")
+        if "SQ_INSTS_LDS" in m:
+            lines.append(f"- LDS instructions per key (wave-wide): {m['SQ_INSTS_LDS'] / slots:.2f}")
+        if "SQ_LDS_BANK_CONFLICT" in m:
+            lines.append(f"- LDS bank-conflict cycles per CU / busy cycles: {m['SQ_LDS_BANK_CONFLICT'] / cus / cyc:.2f}")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -109,6 +143,11 @@ def main():
     a.add_argument("csv")
     a.add_argument("--command", required=True)
     a.add_argument("--title", default="rocprofv3 kernel statistics")
+    c = sub.add_parser("activity")
+    c.add_argument("csv", nargs="+")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--keys", type=int, required=True)
+    c.add_argument("--commands", nargs="+", required=True)
     b = sub.add_parser("counters")
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
@@ -123,6 +162,8 @@ def main():
     args = ap.parse_args()
     if args.cmd == "stats":
         print(stats(args.csv, args.command, args.title), end="")
+    elif args.cmd == "activity":
+        print(activity(args.csv, args.kernel, args.keys, args.commands), end="")
     else:
         print(counters(args.fetch_csv, args.write_csv, args.copy_gib, args.kernel, args.precision, args.schedule,
                        args.command_fetch, args.command_write, args.json, args.alg_bytes), end="")
