@@ -21,7 +21,7 @@ namespace vjb {
 // table, two workgroups per compute unit) or the 15-bit ones (128 KiB).
 // Segments [s_begin, s_end) belong to this launch; the counter counts from 0.
 template <int PREC, bool NARROW, int WG, int UNROLL, int LPF>
-__global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG>::waves_per_eu)) void k_scan_batch(
+__global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, true>::waves_per_eu)) void k_scan_batch(
     const JobDev* __restrict__ jobs, const BatchSeg* __restrict__ segs, uint32_t* __restrict__ next_seg, int s_begin,
     int s_end, const int32_t* __restrict__ job_seg, WgBest* __restrict__ seg_best) {
     using Wt = typename ScanTypes<PREC>::W;
@@ -92,6 +92,7 @@ static const void* batch_kernel_ptr(int schedule) {
     case 5: return (const void*)k_scan_batch<PREC, NARROW, 512, 8, 32>;
     case 6: return (const void*)k_scan_batch<PREC, NARROW, 512, 10, 64>;
     case 7: return (const void*)k_scan_batch<PREC, NARROW, 256, 8, 16>;
+    case 8: return (const void*)k_scan_batch<PREC, NARROW, 1024, 4, 16>;
     default: return (const void*)k_scan_batch<PREC, NARROW, 512, 8, 16>;
     }
 }

@@ -16,7 +16,7 @@ namespace vjb {
 // take group-steps of features; each workgroup leaves its best candidate
 // (the first level of the argmin).
 template <int PREC, bool NARROW, int WG, int UNROLL, int LPF>
-__global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG>::waves_per_eu)) void k_scan(JobDev jd, double2* __restrict__ ferr) {
+__global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, false>::waves_per_eu)) void k_scan(JobDev jd, double2* __restrict__ ferr) {
     using Wt = typename ScanTypes<PREC>::W;
     constexpr int NG = (WG / 64) * (64 / LPF);
     __shared__ ScanLds<Wt, TabCap<PREC, NARROW>::value, NG> lds;
@@ -49,6 +49,7 @@ __global__ __launch_bounds__(kUpdWg) void k_update(JobDev jd, int n_wg) {
 struct Schedule { int wg, unroll, lanes; };
 static const Schedule kSchedules[] = {
     {512, 8, 16}, {512, 10, 16}, {512, 6, 16}, {512, 4, 16}, {1024, 8, 16}, {512, 8, 32}, {512, 10, 64}, {256, 8, 16},
+    {1024, 4, 16},
 };
 constexpr int kNumSchedules = (int)(sizeof(kSchedules) / sizeof(kSchedules[0]));
 
@@ -62,6 +63,7 @@ static const void* scan_kernel_ptr(int schedule) {
     case 5: return (const void*)k_scan<PREC, NARROW, 512, 8, 32>;
     case 6: return (const void*)k_scan<PREC, NARROW, 512, 10, 64>;
     case 7: return (const void*)k_scan<PREC, NARROW, 256, 8, 16>;
+    case 8: return (const void*)k_scan<PREC, NARROW, 1024, 4, 16>;
     default: return (const void*)k_scan<PREC, NARROW, 512, 8, 16>;
     }
 }

@@ -28,12 +28,16 @@ struct TabCap {
 };
 
 // Waves per SIMD the scan kernels are compiled for: the LDS table admits two
-// workgroups per compute unit when it is at most 64 KiB, else one; never
-// fewer than 128 VGPRs per lane (the key batch lives in registers).
-template <int PREC, bool NARROW, int WG>
+// workgroups per compute unit when it is at most 64 KiB, else one.  Batches
+// of more than 4 key units need up to 128 VGPRs per lane (the batch lives in
+// registers), so those launches stay at 4 waves per SIMD; the single-job
+// kernel with 4-unit batches fits in 64 VGPRs and may run 8 (the batched
+// kernel, which also holds the table refill, would spill there).
+template <int PREC, bool NARROW, int WG, int UNROLL, bool BATCHED>
 struct ScanOccupancy {
     static constexpr int wgs = TabCap<PREC, NARROW>::value * (int)sizeof(typename ScanTypes<PREC>::W) <= 65536 ? 2 : 1;
-    static constexpr int waves_per_eu = wgs * WG / 256 < 4 ? wgs * WG / 256 : 4;   // at most 128 VGPRs
+    static constexpr int cap = UNROLL <= 4 && !BATCHED ? 8 : 4;
+    static constexpr int waves_per_eu = wgs * WG / 256 < cap ? wgs * WG / 256 : cap;
 };
 
 __device__ __forceinline__ bool better(const WgBest& c, const WgBest& b) {

@@ -37,7 +37,7 @@ def _datasets(specs):
     return [synth.make_job(seed, p, m, size=s, r0=r0, contrast=c) for seed, p, m, s, r0, c in specs]
 
 
-@pytest.mark.parametrize("precision", ["fp32_wide", "fp32_kahan"])
+@pytest.mark.parametrize("precision", ["fp32_wide", "fp32_kahan", "fp64", "fp32"])
 def test_batch_equals_plain_uneven(precision):
     specs = [((700, 0), 300, 600, 24, 7, 80.0), ((700, 1), 40, 90, 16, 5, 120.0),
              ((700, 2), 1500, 3000, 20, 6, 60.0), ((700, 3), 5, 7, 12, 4, 90.0),

@@ -107,6 +107,43 @@ def test_rounds_teacher_forced(cfg0, precision):
     tr.close()
 
 
+def _dyadic_weights(seed, n):
+    """Integer weights 1..1000 scaled by 2^-m with a sum of exactly 1: every
+    normalised weight, FP32 table entry and prefix sum (multiples of 2^-m, at
+    most 1 in magnitude, m <= 24) is exact in every precision."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, 1001, size=n).astype(np.int64)
+    m = int(np.ceil(np.log2(k.sum())))
+    k[int(rng.integers(0, n))] += (1 << m) - int(k.sum())
+    assert k.sum() == 1 << m and m <= 24 and (k > 0).all()
+    return k.astype(np.float64) / float(1 << m)
+
+
+@pytest.mark.parametrize("precision", ["fp32_wide", "fp64", "fp32_kahan", "fp32"])
+def test_exact_arithmetic_dyadic_weights(cfg0, precision):
+    """With weights on a coarse dyadic grid no operation rounds, on either
+    side: every feature's errors, the stump and its error equal the oracle's
+    bit for bit, in every precision."""
+    images, labels, otr = cfg0
+    cases = [(images, labels, otr, 31)]
+    ti, tl = synth.small_job((205, 1), 300, 8, 4)
+    cases.append((ti, tl, oracle.Trainer(ti, tl), 32))
+    for images_c, labels_c, otr_c, seed in cases:
+        say(f"exact dyadic weights, {precision}, n = {len(labels_c)}")
+        w = _dyadic_weights(seed, len(labels_c))
+        tr = _trainer(images_c, labels_c, precision=precision)
+        tr.set_weights(w)
+        rec, ferr = tr.round(feature_err=True)
+        ferr = ferr.cpu().numpy()
+        orec, ost = otr_c.round(weights=w)
+        assert np.array_equal(ferr[:, 0], ost["err_pos"])
+        assert np.array_equal(ferr[:, 1], ost["err_neg"])
+        assert (rec.feature, rec.polarity, rec.threshold, rec.split_rank) == \
+            (orec.feature, orec.polarity, orec.theta, orec.split)
+        assert rec.error_raw == orec.err_raw
+        tr.close()
+
+
 def test_free_running_matches_oracle(cfg0):
     images, labels, _ = cfg0
     say("cfg0: 5 free-running rounds fp32_wide")
