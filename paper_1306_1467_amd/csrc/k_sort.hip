@@ -1,12 +1,19 @@
 // One-time preparation of every feature: evaluate the Haar feature on all
 // windows (Section 2.2), order the windows by value, and write the per-feature
 // keys (window index + end-of-run flag) in the lane-segment layout that the
-// per-round scan reads.  Feature values never reach HBM: each workgroup holds
-// one feature's n values in LDS, packed with their window index as
-// ((v - vmin) << ib) | i in 32 bits, and sorts them there (bitonic network).
+// per-round scan reads.  Feature values never reach HBM.
+//
+// One workgroup per feature at a time.  Each thread holds C values in
+// registers (window r = k * NT + t in slot k), packed with the window index as
+// ((v - vmin) << ib) | r in 32 bits, and the workgroup sorts them with a
+// stable least-significant-digit radix sort over the value bits only, 4 bits
+// per pass: windows with equal values keep index order, which is the (value,
+// index) order.  A pass ranks each item among the items of its wave and slot
+// with the same digit (ballots), counts items per (digit, slot, wave) in LDS,
+// scans the counts in that order, and scatters through one LDS buffer.
 // A feature whose value range does not fit beside the index in 32 bits
 // (possible only for n > 16384) is sorted as 64-bit pairs in a per-workgroup
-// global scratch buffer instead.
+// global scratch buffer (bitonic network) instead.
 #include <limits.h>
 
 #include "launch.h"
@@ -70,20 +77,65 @@ __device__ void emit_keys(const JobDev& jd, int64_t j, const T* s, int shift, ui
     }
 }
 
-template <int NT>
+constexpr int kRadixBits = 4;
+constexpr int kDigits = 1 << kRadixBits;
+
+// Exclusive prefix sum, in place, of m 16-bit counters (m <= NT * E); thread t
+// owns entries [t * E, t * E + E).  Totals stay below 2^16 (at most n items).
+template <int NT, int E>
+__device__ __forceinline__ void scan_counts(uint16_t* cnt, int m, uint32_t* wtot) {
+    constexpr int NW = NT / 64;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint32_t c[E];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int idx = t * E + e;
+        c[e] = idx < m ? cnt[idx] : 0u;
+        sum += c[e];
+    }
+    // inclusive scan of the per-thread sums within the wave
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    uint32_t base = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) base += w < wv ? wtot[w] : 0u;
+    uint32_t run = base + incl - sum;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int idx = t * E + e;
+        if (idx < m) cnt[idx] = (uint16_t)run;
+        run += c[e];
+    }
+}
+
+template <int NT, int C>
 __global__ __launch_bounds__(NT) void k_sort(JobDev jd, int64_t npow2, int ib, uint64_t* __restrict__ scratch) {
-    extern __shared__ __align__(16) uint32_t s[];
-    __shared__ int32_t rmin[NT / 64], rmax[NT / 64];
+    constexpr int NW = NT / 64;
+    constexpr int NCNT = kDigits * C * NW;                 // counters in (digit, slot, wave) order
+    constexpr int E = (NCNT + NT - 1) / NT;                 // counters per thread in the scan
+    extern __shared__ __align__(16) uint32_t buf[];         // NT * C sorted words, then the counters
+    __shared__ int32_t rmin[NW], rmax[NW];
+    __shared__ uint32_t wtot[NW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t n = jd.g.n;
     const int wp1 = jd.W + 1;
     const uint32_t imask = (1u << ib) - 1u;
+    uint16_t* cnt = (uint16_t*)(buf + NT * C);
     for (int64_t j = blockIdx.x; j < jd.F; j += gridDim.x) {
         const uint32_t desc = jd.ftab[j];
+        // values go through the LDS buffer (bounded register use), then the
+        // packed words into registers
         int32_t vmin = INT_MAX, vmax = INT_MIN;
         for (int64_t i = tid; i < n; i += NT) {
             const int32_t v = haar_value(jd.ii, jd.ii_stride, wp1, desc, i);
-            s[i] = (uint32_t)v;
+            buf[i] = (uint32_t)v;
             vmin = v < vmin ? v : vmin;
             vmax = v > vmax ? v : vmax;
         }
@@ -96,22 +148,65 @@ __global__ __launch_bounds__(NT) void k_sort(JobDev jd, int64_t npow2, int ib, u
         if (lane == 0) { rmin[wv] = vmin; rmax[wv] = vmax; }
         __syncthreads();
         vmin = rmin[0]; vmax = rmax[0];
-        for (int k = 1; k < NT / 64; ++k) {
+        for (int k = 1; k < NW; ++k) {
             vmin = rmin[k] < vmin ? rmin[k] : vmin;
             vmax = rmax[k] > vmax ? rmax[k] : vmax;
         }
         const uint32_t range = (uint32_t)(vmax - vmin);
         const int rb = range == 0 ? 0 : 32 - __clz(range);
         if (rb + ib <= 32) {
-            for (int64_t i = tid; i < npow2; i += NT)
-                s[i] = i < n ? (((uint32_t)((int32_t)s[i] - vmin)) << ib) | (uint32_t)i : 0xFFFFFFFFu;
+            // packed words; slots past n hold all-ones sentinels, which carry
+            // digit 15 in every pass and start after every window, so they
+            // stay behind the windows (the passes need no bounds checks)
+            for (int i = tid; i < NT * C; i += NT)
+                buf[i] = i < n ? (((uint32_t)((int32_t)buf[i] - vmin)) << ib) | (uint32_t)i : 0xFFFFFFFFu;
             __syncthreads();
-            bitonic_sort<NT, uint32_t>(s, npow2);
-            emit_keys<NT, uint32_t>(jd, j, s, ib, imask);
+            uint32_t it[C];
+#pragma unroll
+            for (int k = 0; k < C; ++k) it[k] = buf[k * NT + tid];
+            for (int sh = ib; sh < ib + rb; sh += kRadixBits) {
+                for (int e = tid; e < NCNT; e += NT) cnt[e] = 0;
+                __syncthreads();
+                uint32_t rkp[(C + 3) / 4];   // rank in wave (< 64) of slot k in byte k % 4 of rkp[k / 4]
+#pragma unroll
+                for (int q = 0; q < (C + 3) / 4; ++q) rkp[q] = 0u;
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    const uint32_t d = (it[k] >> sh) & (kDigits - 1);
+                    uint64_t m = ~0ull;
+#pragma unroll
+                    for (int b = 0; b < kRadixBits; ++b) {
+                        const bool bit = (d >> b) & 1u;
+                        const uint64_t bb = __ballot(bit);
+                        m &= bit ? bb : ~bb;
+                    }
+                    const uint32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    rkp[k / 4] |= rk << (8 * (k % 4));
+                    if (rk == 0) cnt[((int)d * C + k) * NW + wv] = (uint16_t)__popcll(m);
+                    // one slot's ballots at a time: interleaving slots would
+                    // keep many wave masks live in scalar registers
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                __syncthreads();
+                scan_counts<NT, E>(cnt, NCNT, wtot);
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    const uint32_t d = (it[k] >> sh) & (kDigits - 1);
+                    const uint32_t rk = (rkp[k / 4] >> (8 * (k % 4))) & 0xFFu;
+                    buf[cnt[((int)d * C + k) * NW + wv] + rk] = it[k];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < C; ++k) it[k] = buf[k * NT + tid];
+            }
+            __syncthreads();
+            emit_keys<NT, uint32_t>(jd, j, buf, ib, imask);
         } else {
             uint64_t* g = scratch + (int64_t)blockIdx.x * npow2;
             for (int64_t i = tid; i < npow2; i += NT)
-                g[i] = i < n ? (((uint64_t)(uint32_t)((int32_t)s[i] - vmin)) << 32) | (uint64_t)i : ~0ull;
+                g[i] = i < n ? (((uint64_t)(uint32_t)((int32_t)buf[i] - vmin)) << 32) | (uint64_t)i : ~0ull;
             __syncthreads();
             bitonic_sort<NT, uint64_t>(g, npow2);
             emit_keys<NT, uint64_t>(jd, j, g, 32, 0xFFFFFFFFull);
@@ -120,13 +215,13 @@ __global__ __launch_bounds__(NT) void k_sort(JobDev jd, int64_t npow2, int ib, u
     }
 }
 
-int sort_launch(const JobDev& jd, uint64_t* scratch, int num_cu, hipStream_t s) {
-    constexpr int NT = 1024;
+template <int NT, int C>
+static int sort_launch_c(const JobDev& jd, uint64_t* scratch, int num_cu, hipStream_t s) {
     const int64_t n = jd.g.n;
-    const int64_t npow2 = sort_pow2(n);
-    const int ib = n <= 1 ? 1 : 32 - __builtin_clz((unsigned)(n - 1));
-    const size_t lds = (size_t)npow2 * sizeof(uint32_t);
-    const void* k = (const void*)k_sort<NT>;
+    int64_t npow2 = sort_pow2(n);
+    int ib = n <= 1 ? 1 : 32 - __builtin_clz((unsigned)(n - 1));
+    const size_t lds = (size_t)NT * C * sizeof(uint32_t) + (size_t)kDigits * C * (NT / 64) * sizeof(uint16_t);
+    const void* k = (const void*)k_sort<NT, C>;
     VJB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     VJB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, NT, lds));
@@ -143,12 +238,23 @@ int sort_launch(const JobDev& jd, uint64_t* scratch, int num_cu, hipStream_t s) 
     }
     JobDev a = jd;
     void* args[] = {(void*)&a, (void*)&npow2, (void*)&ib, (void*)&scratch};
-    int ibv = ib;
-    args[2] = (void*)&ibv;
-    int64_t np = npow2;
-    args[1] = (void*)&np;
     VJB_HIP(hipLaunchKernel(k, dim3((unsigned)grid), dim3(NT), args, lds, s));
     return BOOST_OK;
+}
+
+// C values per thread: the smallest that covers n (n <= 32767).
+int sort_launch(const JobDev& jd, uint64_t* scratch, int num_cu, hipStream_t s) {
+    const int64_t n = jd.g.n;
+    if (n <= 256) return sort_launch_c<256, 1>(jd, scratch, num_cu, s);
+    if (n <= 512) return sort_launch_c<256, 2>(jd, scratch, num_cu, s);
+    if (n <= 1024) return sort_launch_c<256, 4>(jd, scratch, num_cu, s);
+    if (n <= 2048) return sort_launch_c<256, 8>(jd, scratch, num_cu, s);
+    if (n <= 4096) return sort_launch_c<1024, 4>(jd, scratch, num_cu, s);
+    if (n <= 8192) return sort_launch_c<1024, 8>(jd, scratch, num_cu, s);
+    if (n <= 16384) return sort_launch_c<1024, 16>(jd, scratch, num_cu, s);
+    if (n <= 32768) return sort_launch_c<512, 64>(jd, scratch, num_cu, s);
+    set_error("too many windows for the sort");
+    return BOOST_E_INVALID;
 }
 
 }  // namespace vjb
