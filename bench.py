@@ -43,28 +43,38 @@ def profiled_traffic(kind: str, precision: str, schedule: int):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(images, labels, n_features: int, rounds: int):
-    """The FP64 oracle's round on a bounded sample of features, scaled to all."""
+def cpu_baseline(images, labels, n_features: int, rounds: int, rounds_1t: int):
+    """The FP64 oracle's round time on the host cores: `rounds` rounds with
+    every host thread and `rounds_1t` rounds with one thread, over the first
+    `n_features` features (0: all) of the same windows."""
     import numpy as np
     import oracle
     F = oracle.feature_count(24, 24)
     feats = oracle.enumerate_features(24, 24)
-    rng = np.random.default_rng(0)
-    pick = np.sort(rng.choice(F, n_features, replace=False))
+    nf = F if n_features <= 0 or n_features >= F else n_features
+    pick = np.arange(F) if nf == F else np.sort(np.random.default_rng(0).choice(F, nf, replace=False))
     threads = oracle.max_threads()
     ii = oracle.integrals(images, threads)
     vals = oracle.feature_values(ii, feats[pick], threads)
     order = oracle.sort_features(vals, threads)
     w = oracle.init_weights(labels)
-    scratch = np.zeros(n_features, oracle.STUMP_DTYPE)
+    scratch = np.zeros(nf, oracle.STUMP_DTYPE)
     oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)   # warm caches
     t0 = time.perf_counter()
     for _ in range(rounds):
         oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)
     dt = (time.perf_counter() - t0) / rounds
-    return {"value": round(dt * 1e3 * F / n_features, 2), "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": f"{rounds} oracle rounds over {n_features:,} of {F:,} features x {len(labels):,} windows, "
-                      f"scaled by {F / n_features:.3f} (one-time value/sort preparation excluded)"}
+    t0 = time.perf_counter()
+    for _ in range(rounds_1t):
+        oracle.boost_round(vals, order, labels, w, 1e-10, 1, scratch)
+    dt1 = (time.perf_counter() - t0) / max(rounds_1t, 1)
+    scale = F / nf
+    what = "all" if nf == F else f"{nf:,} sampled"
+    return {"value": round(dt * 1e3 * scale, 2), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"{rounds} oracle rounds over {what} of {F:,} features x {len(labels):,} windows"
+                      + ("" if nf == F else f", scaled by {scale:.3f}")
+                      + " (one-time value/sort preparation excluded)",
+            "one_thread_ms": round(dt1 * 1e3 * scale, 1), "one_thread_rounds": rounds_1t}
 
 
 def run_single(args, torch, vb, synth):
@@ -94,6 +104,18 @@ def run_single(args, torch, vb, synth):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     graph_ms = ev0.elapsed_time(ev1) / args.steps
+    # per-round distribution (outside the timed region): HIP events around
+    # each single-round graph launch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    with torch.cuda.stream(tr.stream):
+        evs[0].record()
+    for r in range(args.steps):
+        vb.boost_train(tr.ctx, 1, False)
+        with torch.cuda.stream(tr.stream):
+            evs[r + 1].record()
+    tr.stream.synchronize()
+    per_round = sorted(evs[r].elapsed_time(evs[r + 1]) for r in range(args.steps))
+    pct = lambda q: per_round[min(len(per_round) - 1, int(q * len(per_round)))]
     rec = tr.round()
     tr.close()
     # per-kernel device times: the same rounds with HIP events around each
@@ -116,6 +138,7 @@ def run_single(args, torch, vb, synth):
     out = {
         "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
         "graph_event_ms_per_round": round(graph_ms, 4),
+        "round_ms_p10_p50_p90": [round(pct(0.1), 4), round(pct(0.5), 4), round(pct(0.9), 4)],
         "event_instrumented_ms_per_round": round(timed_ms, 4),
         "init_ms": round(init_ms, 1),
         "scan_ms_avg": round(scan_avg, 4),
@@ -196,8 +219,9 @@ def main():
     ap.add_argument("--precision", default="fp32_wide")
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-features", type=int, default=12000)
-    ap.add_argument("--cpu-rounds", type=int, default=2)
+    ap.add_argument("--cpu-features", type=int, default=0, help="oracle features (0: all)")
+    ap.add_argument("--cpu-rounds", type=int, default=20)
+    ap.add_argument("--cpu-rounds-1t", type=int, default=1)
     ap.add_argument("--batched-configs", default="3",
                     help="comma list of batched workloads to measure (3: 32 jobs, 4: 64 jobs); empty for none")
     ap.add_argument("--batch-rounds", type=int, default=0, help="rounds per batched job (0: the workload's own)")
@@ -243,6 +267,7 @@ def main():
                    "schedule": args.schedule, "features": res["F"], "windows": res["n"]},
         "init_ms": res["init_ms"],
         "graph_event_ms_per_round": res["graph_event_ms_per_round"],
+        "round_ms_p10_p50_p90": res["round_ms_p10_p50_p90"],
         "event_instrumented_ms_per_round": res["event_instrumented_ms_per_round"],
         "scan_ms_avg": res["scan_ms_avg"],
         "update_ms_avg": res["update_ms_avg"],
@@ -252,7 +277,7 @@ def main():
     for cfg in [c for c in args.batched_configs.split(",") if c.strip()]:
         line[f"batched_config{int(cfg)}"] = run_batched(int(cfg), args, torch, vb, synth)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(images, labels, args.cpu_features, args.cpu_rounds)
+        line["cpu_baseline"] = cpu_baseline(images, labels, args.cpu_features, args.cpu_rounds, args.cpu_rounds_1t)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
