@@ -78,7 +78,7 @@ def cpu_baseline(images, labels, n_features: int, rounds: int, rounds_1t: int):
 
 
 def run_single(args, torch, vb, synth):
-    spec = synth.config_jobs(1)[0]
+    spec = synth.workload_jobs("faces15k")[0]
     images, labels = spec.make()
     t0 = time.perf_counter()
     tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=args.precision,
@@ -134,7 +134,7 @@ def run_single(args, torch, vb, synth):
     scan_avg = scan_ms / nr
     alg_bytes = F * n * 2
     achieved = alg_bytes / (scan_avg * 1e-3) / 1e9
-    traffic = profiled_traffic("config1", args.precision, args.schedule)
+    traffic = profiled_traffic("faces15k", args.precision, args.schedule)
     out = {
         "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
         "graph_event_ms_per_round": round(graph_ms, 4),
@@ -156,12 +156,12 @@ def run_single(args, torch, vb, synth):
     return out, images, labels
 
 
-def run_batched(config, args, torch, vb, synth):
+def run_batched(name, args, torch, vb, synth):
     """Jobs of a batched workload trained together (one scan + one update
     launch per round for all jobs) against the same jobs trained one at a
     time through the single-job path, same precision and schedule."""
     import numpy as np
-    specs = synth.config_jobs(config)
+    specs = synth.workload_jobs(name)
     data = [s.make() for s in specs]
     rounds = args.batch_rounds or specs[0].rounds
     prec = args.batch_precision
@@ -196,7 +196,8 @@ def run_batched(config, args, torch, vb, synth):
     bt.close()
     del bt
     torch.cuda.empty_cache()
-    return {"workload": f"{len(data)} jobs, " + ("24x24 windows" if config == 3 else "16/20/24/28 windows")
+    sizes = sorted({s.size for s in specs})
+    return {"workload": f"{len(data)} jobs, " + "/".join(f"{z}x{z}" for z in sizes) + " windows"
                         + f", {min(s.n for s in specs):,}-{max(s.n for s in specs):,} windows per job",
             "jobs": len(data), "rounds": rounds, "precision": prec, "keys_per_round": keys,
             "batched_jobs_rounds_per_s": round(jr / t_batch, 2),
@@ -222,8 +223,9 @@ def main():
     ap.add_argument("--cpu-features", type=int, default=0, help="oracle features (0: all)")
     ap.add_argument("--cpu-rounds", type=int, default=20)
     ap.add_argument("--cpu-rounds-1t", type=int, default=1)
-    ap.add_argument("--batched-configs", default="3",
-                    help="comma list of batched workloads to measure (3: 32 jobs, 4: 64 jobs); empty for none")
+    ap.add_argument("--batched", default="batch32",
+                    help="comma list of batched workloads to measure (batch32: 32 uneven jobs of 24x24 windows, "
+                         "batch64: 64 jobs of 16-28 px windows); empty for none")
     ap.add_argument("--batch-rounds", type=int, default=0, help="rounds per batched job (0: the workload's own)")
     ap.add_argument("--batch-precision", default="fp32_wide")
     ap.add_argument("--batch-schedule", type=int, default=-1,
@@ -233,7 +235,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
-              "(the path would shard features across GPUs, see DESIGN.md)", file=sys.stderr)
+              "(the path would shard features across GPUs: each scans its share and one all-reduce-min "
+              "picks the stump)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -274,8 +277,8 @@ def main():
         "roofline": res["roofline"],
         "last_round": res["last_round"],
     }
-    for cfg in [c for c in args.batched_configs.split(",") if c.strip()]:
-        line[f"batched_config{int(cfg)}"] = run_batched(int(cfg), args, torch, vb, synth)
+    for name in [c.strip() for c in args.batched.split(",") if c.strip()]:
+        line[f"batched_{name}"] = run_batched(name, args, torch, vb, synth)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(images, labels, args.cpu_features, args.cpu_rounds, args.cpu_rounds_1t)
     else:

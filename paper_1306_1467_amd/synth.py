@@ -157,23 +157,27 @@ class JobSpec:
         return make_job(self.seed, self.n_pos, self.n_neg, self.size, self.r0, self.contrast)
 
 
-def config_jobs(config_id: int):
-    """Job specs of the five workloads.
+WORKLOADS = ("tiny", "faces15k", "batch32", "batch64")
 
-    0: 128 + 128 windows of 24x24, r0 = 7, contrast 110, 5 rounds (parity size).
-    1: 5,000 + 10,000 windows of 24x24, same template, 200 rounds.
-    2: config 1's data (precision sweep).
-    3: 32 jobs, 24x24, positives log-uniform in [500, 5000], negatives twice the
-       positives, r0 ~ U{5..12}, contrast ~ U[60, 140], 50 rounds.
-    4: 64 jobs, window 16/20/24/28, positives log-uniform in [1000, 8000],
-       negatives log-uniform in [2000, 20000], r0 ~ U{5..12},
-       contrast ~ U[60, 140], 100 rounds.
+
+def workload_jobs(name: str):
+    """Job specs of the named workloads.
+
+    tiny:     128 + 128 windows of 24x24, r0 = 7, contrast 110, 5 rounds.
+    faces15k: 5,000 + 10,000 windows of 24x24, same template, 200 rounds
+              (the size of the paper's face training set).
+    batch32:  32 jobs, 24x24, positives log-uniform in [500, 5000], negatives
+              twice the positives, r0 ~ U{5..12}, contrast ~ U[60, 140],
+              50 rounds.
+    batch64:  64 jobs, window 16/20/24/28, positives log-uniform in
+              [1000, 8000], negatives log-uniform in [2000, 20000],
+              r0 ~ U{5..12}, contrast ~ U[60, 140], 100 rounds.
     """
-    if config_id == 0:
+    if name == "tiny":
         return [JobSpec((0,), 128, 128, 24, 7, 110.0, 5)]
-    if config_id in (1, 2):
+    if name == "faces15k":
         return [JobSpec((1,), 5000, 10000, 24, 7, 110.0, 200)]
-    if config_id == 3:
+    if name == "batch32":
         jobs = []
         for j in range(32):
             rng = _rng((3, j, 0))
@@ -182,7 +186,7 @@ def config_jobs(config_id: int):
             c = float(rng.uniform(60, 140))
             jobs.append(JobSpec((3, j), l, 2 * l, 24, r0, c, 50))
         return jobs
-    if config_id == 4:
+    if name == "batch64":
         jobs = []
         for j in range(64):
             rng = _rng((4, j, 0))
@@ -193,7 +197,7 @@ def config_jobs(config_id: int):
             c = float(rng.uniform(60, 140))
             jobs.append(JobSpec((4, j), l, m, s, r0, c, 100))
         return jobs
-    raise ValueError(f"unknown config {config_id}")
+    raise ValueError(f"unknown workload {name!r}")
 
 
 def small_job(seed, n: int, size: int, levels: int = 4, pos_frac: float = 0.5):

@@ -25,15 +25,15 @@ def say(msg):
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    spec = synth.config_jobs(1)[0]
+def faces15k():
+    spec = synth.workload_jobs("faces15k")[0]
     say("generating 15,000 windows")
     images, labels = spec.make()
     return images, labels
 
 
-def test_fullsize_sampled_rounds(cfg1):
-    images, labels = cfg1
+def test_fullsize_sampled_rounds(faces15k):
+    images, labels = faces15k
     n = len(labels)
     say("full size: GPU init (all features)")
     tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision="fp32_wide")
@@ -71,8 +71,8 @@ def test_fullsize_sampled_rounds(cfg1):
     tr.close()
 
 
-def test_fullsize_sorted_sample(cfg1):
-    images, labels = cfg1
+def test_fullsize_sorted_sample(faces15k):
+    images, labels = faces15k
     tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels))
     feats = oracle.enumerate_features(24, 24)
     ii = oracle.integrals(images)

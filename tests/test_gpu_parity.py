@@ -29,8 +29,8 @@ def say(msg):
 
 
 @pytest.fixture(scope="module")
-def cfg0():
-    spec = synth.config_jobs(0)[0]
+def tiny():
+    spec = synth.workload_jobs("tiny")[0]
     images, labels = spec.make()
     say("building oracle for 24x24 x 256")
     otr = oracle.Trainer(images, labels)
@@ -42,9 +42,9 @@ def _trainer(images, labels, **kw):
                       torch.from_numpy(np.ascontiguousarray(labels)), **kw)
 
 
-def test_integral_and_values_exact(cfg0):
-    images, labels, otr = cfg0
-    say("cfg0: integral images + all feature values")
+def test_integral_and_values_exact(tiny):
+    images, labels, otr = tiny
+    say("tiny: integral images + all feature values")
     tr = _trainer(images, labels)
     ii = tr.integral().cpu().numpy()
     assert (ii == otr.ii).all()
@@ -54,9 +54,9 @@ def test_integral_and_values_exact(cfg0):
     tr.close()
 
 
-def test_sorted_keys(cfg0):
-    images, labels, otr = cfg0
-    say("cfg0: sorted keys of all features")
+def test_sorted_keys(tiny):
+    images, labels, otr = tiny
+    say("tiny: sorted keys of all features")
     tr = _trainer(images, labels)
     F, n = otr.vals.shape
     step = 20000
@@ -75,11 +75,11 @@ def test_sorted_keys(cfg0):
 
 
 @pytest.mark.parametrize("precision", ["fp32_wide", "fp64", "fp32_kahan", "fp32"])
-def test_rounds_teacher_forced(cfg0, precision):
+def test_rounds_teacher_forced(tiny, precision):
     """Per round: the oracle's weights go to both sides; every feature's error
     for both polarities, the stump, beta, alpha and the updated weights."""
-    images, labels, otr = cfg0
-    say(f"cfg0: 5 teacher-forced rounds, {precision}")
+    images, labels, otr = tiny
+    say(f"tiny: 5 teacher-forced rounds, {precision}")
     tr = _trainer(images, labels, precision=precision)
     n = len(labels)
     w = oracle.init_weights(labels)
@@ -120,11 +120,11 @@ def _dyadic_weights(seed, n):
 
 
 @pytest.mark.parametrize("precision", ["fp32_wide", "fp64", "fp32_kahan", "fp32"])
-def test_exact_arithmetic_dyadic_weights(cfg0, precision):
+def test_exact_arithmetic_dyadic_weights(tiny, precision):
     """With weights on a coarse dyadic grid no operation rounds, on either
     side: every feature's errors, the stump and its error equal the oracle's
     bit for bit, in every precision."""
-    images, labels, otr = cfg0
+    images, labels, otr = tiny
     cases = [(images, labels, otr, 31)]
     ti, tl = synth.small_job((205, 1), 300, 8, 4)
     cases.append((ti, tl, oracle.Trainer(ti, tl), 32))
@@ -144,9 +144,9 @@ def test_exact_arithmetic_dyadic_weights(cfg0, precision):
         tr.close()
 
 
-def test_free_running_matches_oracle(cfg0):
-    images, labels, _ = cfg0
-    say("cfg0: 5 free-running rounds fp32_wide")
+def test_free_running_matches_oracle(tiny):
+    images, labels, _ = tiny
+    say("tiny: 5 free-running rounds fp32_wide")
     tr = _trainer(images, labels, precision="fp32_wide")
     otr = oracle.Trainer(images, labels)
     n = len(labels)
@@ -320,8 +320,8 @@ def test_schedules_agree():
         tr.close()
 
 
-def test_strong_classifier_matches_oracle(cfg0):
-    images, labels, _ = cfg0
+def test_strong_classifier_matches_oracle(tiny):
+    images, labels, _ = tiny
     say("strong classifier")
     tr = _trainer(images, labels)
     recs = tr.train(5)

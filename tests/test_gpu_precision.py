@@ -64,7 +64,7 @@ def top_two_gap(errs: np.ndarray) -> float:
 
 @pytest.fixture(scope="module")
 def fullsize():
-    images, labels = synth.config_jobs(2)[0].make()
+    images, labels = synth.workload_jobs("faces15k")[0].make()
     ii = oracle.integrals(images)
     feats = oracle.enumerate_features(24, 24)
     rng = np.random.default_rng(21)

@@ -319,13 +319,13 @@ def test_generator_deterministic_and_template():
     assert (a[0] == b[0]).all() and (a[1] == b[1]).all()
     assert a[0].dtype == np.uint8 and a[0].shape == (22, 24, 24)
     assert (a[1][:10] == 1).all() and (a[1][10:] == 0).all()
-    # template levels before blur: band at 60, bright regions at 170 (config 0)
+    # template levels before blur: band at 60, bright regions at 170 (the tiny and faces15k workloads)
     t = np.full((24, 24), 115.0)
     t[2:6, 4:20] = 170; t[7:11, 2:22] = 60; t[12:18, 3:9] = 170; t[12:18, 15:21] = 170
     blurred = synth.gaussian_blur(t, 1.0)
     assert np.allclose(synth.template(7, 110.0), blurred)
     assert abs(synth.gaussian_blur(np.full((5, 5), 3.0), 1.3) - 3.0).max() < 1e-12
-    specs3 = synth.config_jobs(3)
+    specs3 = synth.workload_jobs("batch32")
     assert len(specs3) == 32 and all(500 <= s.n_pos <= 5000 and s.n_neg == 2 * s.n_pos for s in specs3)
-    specs4 = synth.config_jobs(4)
+    specs4 = synth.workload_jobs("batch64")
     assert len(specs4) == 64 and {s.size for s in specs4} <= {16, 20, 24, 28}
