@@ -224,7 +224,13 @@ int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels
     c->n = n;
     c->F = host_feature_count(fs);
     c->stream = (hipStream_t)o->stream;
-    auto fail = [&](int code) { delete c; return code; };
+    // on failure, work already queued on the stream finishes before the call
+    // returns: the caller may free the workspace right away
+    auto fail = [&](int code) {
+        if (c->stream) hipStreamSynchronize(c->stream); else hipDeviceSynchronize();
+        delete c;
+        return code;
+    };
     if (hipGetDevice(&c->device) != hipSuccess ||
         hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
         set_error("no HIP device");

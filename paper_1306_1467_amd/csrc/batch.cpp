@@ -228,7 +228,13 @@ int boost_batch_init(boost_batch** out, int32_t n_jobs, const boost_job* jobs, c
         return BOOST_E_NOMEM;
     }
     boost_batch* b = new boost_batch();
-    auto fail = [&](int code) { delete b; return code; };
+    // on failure, work already queued on the stream finishes before the call
+    // returns: the caller may free the workspace right away
+    auto fail = [&](int code) {
+        if (b->stream) hipStreamSynchronize(b->stream); else hipDeviceSynchronize();
+        delete b;
+        return code;
+    };
     b->n_jobs = n_jobs;
     b->opts = *o;
     b->stream = (hipStream_t)o->stream;
