@@ -54,9 +54,11 @@ def cpu_baseline(images, labels, n_features: int, rounds: int, rounds_1t: int):
     nf = F if n_features <= 0 or n_features >= F else n_features
     pick = np.arange(F) if nf == F else np.sort(np.random.default_rng(0).choice(F, nf, replace=False))
     threads = oracle.max_threads()
+    t_prep = time.perf_counter()
     ii = oracle.integrals(images, threads)
     vals = oracle.feature_values(ii, feats[pick], threads)
     order = oracle.sort_features(vals, threads)
+    t_prep = time.perf_counter() - t_prep
     w = oracle.init_weights(labels)
     scratch = np.zeros(nf, oracle.STUMP_DTYPE)
     oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)   # warm caches
@@ -74,7 +76,19 @@ def cpu_baseline(images, labels, n_features: int, rounds: int, rounds_1t: int):
             "sample": f"{rounds} oracle rounds over {what} of {F:,} features x {len(labels):,} windows"
                       + ("" if nf == F else f", scaled by {scale:.3f}")
                       + " (one-time value/sort preparation excluded)",
-            "one_thread_ms": round(dt1 * 1e3 * scale, 1), "one_thread_rounds": rounds_1t}
+            "one_thread_ms": round(dt1 * 1e3 * scale, 1), "one_thread_rounds": rounds_1t,
+            "prep_s": round(t_prep * scale, 2), "host_cpu": _cpu_model(), "host_threads": os.cpu_count()}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def run_single(args, torch, vb, synth):
