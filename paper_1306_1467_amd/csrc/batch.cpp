@@ -189,7 +189,7 @@ static int tune_part(boost_batch* b, int p) {
         if ((rc = upload_segments(b)) != BOOST_OK || (rc = time_part(b, p, ms)) != BOOST_OK) return rc;
         if (ms < best_ms) { best_ms = ms; best = pc; }
     }
-    static const int kSpw[] = {2, 8, 16, 32};
+    static const int kSpw[] = {4, 8, 32};   // tried with the best schedule (kSegsPerWg was tried with each)
     b->part[p] = best;
     for (int spw : kSpw) {
         PartCfg pc = best;

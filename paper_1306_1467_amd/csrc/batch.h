@@ -25,7 +25,7 @@ struct BatchDev {
 };
 
 constexpr int kGatherRounds = 256;   // records gathered per copy
-constexpr int kSegsPerWg = 4;        // work-queue granularity: segments per scan workgroup on average
+constexpr int kSegsPerWg = 16;       // work-queue granularity without tuning: segments per scan workgroup on average
 constexpr int kMaxSegsPerWg = 32;    // the largest granularity the tuner tries
 constexpr int kMaxJobs = 4096;
 

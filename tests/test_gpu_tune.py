@@ -76,7 +76,7 @@ def test_auto_batch_per_key_format():
     bt.close()
     # the fixed default schedule gives the same stumps, bit for bit
     bt = vb.BatchTrainer(ds)
-    assert bt.schedule() == [(0, 4), (0, 4)]
+    assert bt.schedule() == [(0, 16), (0, 16)]
     ref = bt.train(5)
     bt.close()
     assert recs.tobytes() == ref.tobytes()
@@ -85,7 +85,7 @@ def test_auto_batch_per_key_format():
 def test_batch_schedule_absent_format():
     images, labels = synth.make_job((820, 0), 50, 60, size=12)
     bt = vb.BatchTrainer([(torch.from_numpy(images), torch.from_numpy(labels))])
-    assert bt.schedule() == [(0, 4), (-1, 0)]
+    assert bt.schedule() == [(0, 16), (-1, 0)]
     with pytest.raises(vb.BoostError):
         vb.boost_batch_get_schedule(bt.ctx, 2)
     bt.close()
