@@ -94,11 +94,16 @@ def _cpu_model() -> str:
 def run_single(args, torch, vb, synth):
     spec = synth.workload_jobs("faces15k")[0]
     images, labels = spec.make()
+    vb.boost_tune_cache_clear()
     t0 = time.perf_counter()
     tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=args.precision,
                     schedule_id=args.schedule)
     torch.cuda.synchronize()
     init_ms = (time.perf_counter() - t0) * 1e3
+    # the schedule in use (under the measured choice: the tuner's pick, timed during init)
+    schedule, tune_ms = tr.schedule()
+    tuning = {"requested": args.schedule, "chosen": schedule,
+              "best_scan_ms_by_schedule": {str(k): round(m, 4) for k, m in enumerate(tune_ms) if m > 0}}
     F, n = tr.F, tr.n
     if args.warmup:
         vb.boost_train(tr.ctx, args.warmup, False)
@@ -135,7 +140,7 @@ def run_single(args, torch, vb, synth):
     # per-kernel device times: the same rounds with HIP events around each
     # kernel on the library's stream (direct launches)
     tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=args.precision,
-                    schedule_id=args.schedule, flags=vb.BOOST_FLAG_TIMING)
+                    schedule_id=schedule, flags=vb.BOOST_FLAG_TIMING)
     if args.warmup:
         vb.boost_train(tr.ctx, args.warmup, False)
     vb.boost_reset_timing(tr.ctx)
@@ -148,7 +153,7 @@ def run_single(args, torch, vb, synth):
     scan_avg = scan_ms / nr
     alg_bytes = F * n * 2
     achieved = alg_bytes / (scan_avg * 1e-3) / 1e9
-    traffic = profiled_traffic("faces15k", args.precision, args.schedule)
+    traffic = profiled_traffic("faces15k", args.precision, schedule)
     out = {
         "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
         "graph_event_ms_per_round": round(graph_ms, 4),
@@ -162,9 +167,10 @@ def run_single(args, torch, vb, synth):
                      "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                                          "copy-calibrated)",
                      "traffic_GBps": None if traffic is None else round(traffic / (scan_avg * 1e-3) / 1e9, 1),
-                     "kernel": "k_scan", "alg_bytes_per_launch": alg_bytes},
+                     "kernel": f"k_scan (schedule {schedule})", "alg_bytes_per_launch": alg_bytes},
         "last_round": {"feature": int(rec.feature), "error_raw": rec.error_raw, "polarity": int(rec.polarity),
                        "threshold": int(rec.threshold)},
+        "schedule_tuning": tuning, "schedule": schedule,
         "F": F, "n": n,
     }
     return out, images, labels
@@ -232,7 +238,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="fp32_wide")
-    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=-1,
+                    help="scan launch schedule of the single-job workload (-1: measured choice at init)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-features", type=int, default=0, help="oracle features (0: all)")
     ap.add_argument("--cpu-rounds", type=int, default=20)
@@ -281,7 +288,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "162,336 Haar features x 15,000 windows 24x24 (5,000 pos + 10,000 neg), "
                                "one boosting round per step", "precision": args.precision,
-                   "schedule": args.schedule, "features": res["F"], "windows": res["n"]},
+                   "schedule": res["schedule"], "schedule_requested": args.schedule, "features": res["F"],
+                   "windows": res["n"]},
         "init_ms": res["init_ms"],
         "graph_event_ms_per_round": res["graph_event_ms_per_round"],
         "round_ms_p10_p50_p90": res["round_ms_p10_p50_p90"],
@@ -290,6 +298,7 @@ def main():
         "update_ms_avg": res["update_ms_avg"],
         "roofline": res["roofline"],
         "last_round": res["last_round"],
+        "schedule_tuning": res["schedule_tuning"],
     }
     for name in [c.strip() for c in args.batched.split(",") if c.strip()]:
         line[f"batched_{name}"] = run_batched(name, args, torch, vb, synth)
