@@ -37,10 +37,9 @@ def profiled_traffic(kind: str, precision: str, schedule: int):
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if (d.get("scan_source_hash") != scan_source_hash() or d.get("precision") != precision
-            or d.get("schedule") != schedule):
+    if d.get("scan_source_hash") != scan_source_hash() or d.get("precision") != precision:
         return None
-    return d.get("bytes_per_launch")
+    return d.get("schedules", {}).get(str(schedule), {}).get("bytes_per_launch")
 
 
 def cpu_baseline(images, labels, n_features: int, rounds: int, rounds_1t: int):

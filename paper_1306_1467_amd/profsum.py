@@ -81,13 +81,23 @@ def counters(fetch_csv: str, write_csv: str, copy_gib: float, kernel: str, preci
     fetch_b = statistics.mean(fk) * 1024.0 / ff
     write_b = statistics.mean(wk) * 1024.0 / wf
     total = fetch_b + write_b
-    rec = {"kernel": kernel, "precision": precision, "schedule": schedule, "scan_source_hash": scan_source_hash(),
-           "bytes_per_launch": round(total), "fetch_bytes_per_launch": round(fetch_b),
+    rec = {"kernel": kernel, "bytes_per_launch": round(total), "fetch_bytes_per_launch": round(fetch_b),
            "write_bytes_per_launch": round(write_b), "fetch_counter_per_byte": ff, "write_counter_per_byte": wf,
            "copy_bytes": copy_bytes, "launches": [len(fk), len(wk)]}
     if json_out:
+        # one record per schedule; records of other schedules are kept while
+        # the scan sources and the precision are unchanged
+        doc = {"scan_source_hash": scan_source_hash(), "precision": precision, "schedules": {}}
+        try:
+            with open(json_out) as f:
+                old = json.load(f)
+            if old.get("scan_source_hash") == doc["scan_source_hash"] and old.get("precision") == precision:
+                doc["schedules"].update(old.get("schedules", {}))
+        except (OSError, ValueError):
+            pass
+        doc["schedules"][str(schedule)] = rec
         with open(json_out, "w") as f:
-            json.dump(rec, f, indent=1)
+            json.dump(doc, f, indent=1)
             f.write("\n")
     lines = ["# HBM traffic per launch of `" + kernel + "`", "",
              "FETCH_SIZE pass:", "", "```", cmd_fetch, "```", "", "WRITE_SIZE pass:", "", "```", cmd_write, "```", "",
@@ -102,7 +112,7 @@ def counters(fetch_csv: str, write_csv: str, copy_gib: float, kernel: str, preci
     if alg_bytes:
         lines.append(f"Algorithmic bytes per launch: {alg_bytes / 1e9:.4f} GB; measured / algorithmic = "
                      f"{total / alg_bytes:.4f}.")
-    lines.append(f"Precision {precision}, schedule {schedule}, scan source hash {rec['scan_source_hash']}.")
+    lines.append(f"Precision {precision}, schedule {schedule}, scan source hash {scan_source_hash()}.")
     return "\n".join(lines) + "\n"
 
 
