@@ -157,7 +157,7 @@ static int launch_part(boost_batch* b, int p) {
 // Times one part's scan under its current configuration (the queue counter is
 // cleared before each launch; the other part is not launched).
 static int time_part(boost_batch* b, int p, double& ms) {
-    return time_launches(b->stream, kTuneReps, [&]() -> int {
+    return time_launches(b->stream, kTuneRepsBatch, [&]() -> int {
         VJB_HIP(hipMemsetAsync(b->bd.next_seg + p, 0, 4, b->stream));
         return launch_part(b, p);
     }, ms);

@@ -41,7 +41,8 @@ int scan_launch(const ScanPlan& p, const JobDev& jd, double2* ferr, hipStream_t 
 int update_launch(const JobDev& jd, int n_wg, hipStream_t s);
 
 // tune.cpp: measured schedule choice
-constexpr int kTuneReps = 3;   // timed launches per candidate (the minimum counts)
+constexpr int kTuneReps = 5;        // timed launches per candidate of a single job (the minimum counts)
+constexpr int kTuneRepsBatch = 3;   // the same for a batch (its launches are longer)
 int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, double& best_ms);
 bool tune_cache_get(const std::string& key, std::vector<int>& choice);
 void tune_cache_put(const std::string& key, const std::vector<int>& choice);

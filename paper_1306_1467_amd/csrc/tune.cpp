@@ -70,20 +70,34 @@ int tune_single(const JobDev& jd, int precision, int num_cu, int device, hipStre
     for (int k = 0; k < scan_schedule_count(); ++k) ms_out[k] = -1.0;
     std::vector<int> hit;
     if (tune_cache_get(key, hit)) { chosen = hit[0]; return BOOST_OK; }
-    chosen = -1;
-    double best = 1e300;
+    std::vector<int> ids;
+    std::vector<ScanPlan> plans;
     for (int k = 0; k < scan_schedule_count(); ++k) {
         if (scan_schedule_lanes(k) != lanes) continue;
         ScanPlan p;
-        int rc = scan_plan(p, precision, jd.g.narrow != 0, k, jd.g.n, jd.F, num_cu);
-        if (rc != BOOST_OK) continue;   // e.g. does not fit on a compute unit
-        double ms = 0;
-        if ((rc = time_launches(s, kTuneReps, [&]() { return scan_launch(p, jd, nullptr, s); }, ms)) != BOOST_OK)
-            return rc;
-        ms_out[k] = ms;
-        if (ms < best) { best = ms; chosen = k; }
+        if (scan_plan(p, precision, jd.g.narrow != 0, k, jd.g.n, jd.F, num_cu) != BOOST_OK) continue;   // does not fit
+        ids.push_back(k);
+        plans.push_back(p);
     }
-    if (chosen < 0) { set_error("no launch schedule fits this job"); return BOOST_E_INVALID; }
+    if (ids.empty()) { set_error("no launch schedule fits this job"); return BOOST_E_INVALID; }
+    // candidates are timed in turn, kTuneReps rounds over all of them, so that
+    // slow drifts of the clock do not favour one; each keeps its fastest launch
+    std::vector<double> best(ids.size(), 1e300);
+    int rc;
+    for (int rep = 0; rep <= kTuneReps; ++rep)
+        for (size_t c = 0; c < ids.size(); ++c) {
+            double ms = 0;
+            if ((rc = time_launches(s, rep == 0 ? 0 : 1, [&]() { return scan_launch(plans[c], jd, nullptr, s); }, ms)) !=
+                BOOST_OK)
+                return rc;
+            if (rep > 0 && ms < best[c]) best[c] = ms;   // round 0 only warms up
+        }
+    size_t win = 0;
+    for (size_t c = 0; c < ids.size(); ++c) {
+        ms_out[ids[c]] = best[c];
+        if (best[c] < best[win]) win = c;
+    }
+    chosen = ids[win];
     tune_cache_put(key, {chosen});
     return BOOST_OK;
 }
