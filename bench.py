@@ -148,6 +148,7 @@ def run_single(args, torch, vb, synth):
     tr.stream.synchronize()
     timed_ms = (time.perf_counter() - t1) * 1e3 / args.steps
     scan_ms, upd_ms, nr, _ = vb.boost_get_timing(tr.ctx)
+    probe_ms = vb.boost_probe_stream(tr.ctx, 10)   # the same key reads with no arithmetic
     tr.close()
     scan_avg = scan_ms / nr
     alg_bytes = F * n * 2
@@ -169,6 +170,8 @@ def run_single(args, torch, vb, synth):
                      "kernel": f"k_scan (schedule {schedule})", "alg_bytes_per_launch": alg_bytes},
         "last_round": {"feature": int(rec.feature), "error_raw": rec.error_raw, "polarity": int(rec.polarity),
                        "threshold": int(rec.threshold)},
+        "stream_probe": {"ms": round(probe_ms, 4), "key_GBps": round(alg_bytes / (probe_ms * 1e-3) / 1e9, 1),
+                         "scan_time_over_probe": round(probe_ms / scan_avg, 4)},
         "schedule_tuning": tuning, "schedule": schedule,
         "F": F, "n": n,
     }
@@ -297,6 +300,7 @@ def main():
         "update_ms_avg": res["update_ms_avg"],
         "roofline": res["roofline"],
         "last_round": res["last_round"],
+        "stream_probe": res["stream_probe"],
         "schedule_tuning": res["schedule_tuning"],
     }
     for name in [c.strip() for c in args.batched.split(",") if c.strip()]:

@@ -224,6 +224,16 @@ int boost_rounds_done(boost_ctx *c, int32_t *out_rounds);
 int boost_get_timing(boost_ctx *c, double out[4]);
 int boost_reset_timing(boost_ctx *c);
 
+/* Diagnostic: the memory-system ceiling of this context's scan.  Launches
+ * reps + 1 times (the first untimed) a kernel that reads every key exactly as
+ * the scan does (same grid, workgroup size, lane segments and load batches)
+ * with no LDS gathers or sums, and returns in *best_ms the fastest launch
+ * (HIP events on the context's stream; synchronises).  Key bytes (features x
+ * windows x 2) over *best_ms is the bandwidth the scan would reach if its
+ * arithmetic were free.  Weights and results are not changed.
+ * BOOST_E_INVALID for a NULL context or output or reps < 1. */
+int boost_probe_stream(boost_ctx *c, int32_t reps, double *best_ms);
+
 /* Launch schedule in use (the tuner's choice under BOOST_SCHEDULE_AUTO).
  * ms_out NULL or host double[cap]: ms_out[k] = the fastest of the timed scan
  * launches of schedule k during tuning, -1 where schedule k was not timed

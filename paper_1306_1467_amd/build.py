@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvjboost.so")
 
-SOURCES = ["api.cpp", "features.cpp", "batch.cpp", "tune.cpp", "k_prep.hip", "k_sort.hip", "k_scan.hip", "k_batch.hip"]
+SOURCES = ["api.cpp", "features.cpp", "batch.cpp", "tune.cpp", "k_prep.hip", "k_sort.hip", "k_scan.hip", "k_batch.hip", "k_probe.hip"]
 ARCH = os.environ.get("VJBOOST_ARCH", "gfx950")
 
 

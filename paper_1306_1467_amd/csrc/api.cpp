@@ -193,6 +193,16 @@ int boost_schedule_count(int32_t precision) {
     return scan_schedule_count();
 }
 
+int boost_probe_stream(boost_ctx* c, int32_t reps, double* best_ms) {
+    if (!c || !best_ms || reps < 1) { set_error("NULL context or output, or reps < 1"); return BOOST_E_INVALID; }
+    // the per-workgroup candidate records (one per scan workgroup) take the
+    // probe's words; the next round's scan rewrites them
+    uint32_t* sink = (uint32_t*)c->jd.wgb;
+    static_assert(sizeof(WgBest) >= sizeof(uint32_t), "one probe word per scan workgroup record");
+    return time_launches(c->stream, reps, [&]() { return probe_launch(c->plan, c->schedule, c->jd, sink, c->stream); },
+                         *best_ms);
+}
+
 int boost_get_schedule(const boost_ctx* c, double* ms_out, int32_t cap) {
     if (!c) { set_error("NULL context"); return BOOST_E_INVALID; }
     if (ms_out)

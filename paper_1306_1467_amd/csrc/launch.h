@@ -40,6 +40,10 @@ int scan_plan(ScanPlan& p, int precision, bool narrow, int schedule, int64_t n, 
 int scan_launch(const ScanPlan& p, const JobDev& jd, double2* ferr, hipStream_t s);
 int update_launch(const JobDev& jd, int n_wg, hipStream_t s);
 
+// k_probe.hip: reads every key with the scan's access pattern and no arithmetic
+// (one word per workgroup to sink[grid])
+int probe_launch(const ScanPlan& p, int schedule, const JobDev& jd, uint32_t* sink, hipStream_t s);
+
 // tune.cpp: measured schedule choice
 constexpr int kTuneReps = 5;        // timed launches per candidate of a single job (the minimum counts)
 constexpr int kTuneRepsBatch = 3;   // the same for a batch (its launches are longer)

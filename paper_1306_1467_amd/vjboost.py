@@ -85,6 +85,7 @@ _SIGS = {
     "boost_schedule_count": (ctypes.c_int, [ctypes.c_int32]),
     "boost_tune_cache_clear": (None, []),
     "boost_get_schedule": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "boost_probe_stream": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "boost_init": (ctypes.c_int, [ctypes.POINTER(_P), _P, _P, ctypes.c_int64, ctypes.POINTER(FeatureSet),
                                   ctypes.POINTER(Options), _P, ctypes.c_size_t]),
     "boost_round": (ctypes.c_int, [_P, ctypes.POINTER(Stump), _P]),
@@ -238,6 +239,14 @@ def boost_get_schedule(ctx):
     rc = lib().boost_get_schedule(ctx, ctypes.cast(ms, _P), cap)
     _check(min(rc, 0))
     return int(rc), list(ms)
+
+
+def boost_probe_stream(ctx, reps: int = 5) -> float:
+    """Fastest of `reps` launches (ms) of a kernel that reads every key with
+    the scan's access pattern and no arithmetic."""
+    ms = ctypes.c_double(0.0)
+    _check(lib().boost_probe_stream(ctx, reps, ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def boost_tune_cache_clear():

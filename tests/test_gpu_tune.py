@@ -89,3 +89,20 @@ def test_batch_schedule_absent_format():
     with pytest.raises(vb.BoostError):
         vb.boost_batch_get_schedule(bt.ctx, 2)
     bt.close()
+
+
+def test_stream_probe_changes_nothing():
+    images, labels = synth.make_job((830, 0), 500, 900, size=20, r0=6, contrast=40.0)
+    ref = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels))
+    expect = ref.train(4)
+    ref.close()
+    for sched in range(vb.boost_schedule_count()):
+        tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), schedule_id=sched)
+        first = tr.train(2)
+        ms = vb.boost_probe_stream(tr.ctx, 3)
+        assert ms > 0
+        rest = tr.train(2)
+        assert np.concatenate([first, rest]).tobytes() == expect.tobytes(), sched
+        tr.close()
+    with pytest.raises(vb.BoostError):
+        vb.boost_probe_stream(None, 1)
