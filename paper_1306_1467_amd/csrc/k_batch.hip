@@ -1,6 +1,7 @@
 // Batched rounds: many independent jobs (own windows, labels, feature sets)
-// advance one boosting round with one persistent scan launch and one update
-// launch for all of them.
+// advance one boosting round with one persistent scan launch per key format
+// (jobs with 14-bit keys, jobs with 15-bit keys) and one update launch for
+// all of them.
 //
 // The scan's work is cut into segments (job, feature range) of about the same
 // cost; workgroups take segments from a work queue (an atomic counter; every
@@ -8,10 +9,10 @@
 // LDS weight table when the segment's job differs from the previous one
 // (normalisation, Section 2.3 step 1), and leave one candidate per segment.
 // The update launch runs one workgroup per 256 windows of every job; each
-// takes the argmin over its job's segment
-// candidates (Section 3.3.2 step 4a) and updates its windows (Section 2.3
-// step 4).  Per job, the arithmetic is that of the single-job kernels, so the
-// stumps equal those of the job run alone.
+// takes the argmin over its job's segment candidates (Section 3.3.2 step 4a)
+// and updates its windows (Section 2.3 step 4).  Per job, the arithmetic is
+// that of the single-job kernels, so the stumps equal those of the job run
+// alone.
 #include "batch.h"
 #include "round_core.h"
 
