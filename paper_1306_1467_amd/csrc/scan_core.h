@@ -11,11 +11,12 @@
 // h = 1 iff p f < p theta, Section 2.2).  The best split of a feature is thus
 // the largest D_k (p = +1) and the smallest D_k (p = -1) over split points.
 //
-// A wave scans a feature: lane L walks its contiguous segment of ranks,
-// keeping its local running sum and the largest / smallest local sum at a run
-// end; an exclusive wave scan of the lane totals then shifts each lane's
-// extremes to global D values.  max_k (base + L_k) = base + max_k L_k, so one
-// pass over the keys suffices.
+// A group of LPF lanes (16 by default; a wave holds 64 / LPF groups) scans a
+// feature: lane L walks its contiguous segment of ranks, keeping its local
+// running sum and the largest / smallest local sum at a run end; an exclusive
+// scan of the lane totals across the group then shifts each lane's extremes
+// to global D values.  max_k (base + L_k) = base + max_k L_k, so one pass
+// over the keys suffices.
 #pragma once
 
 #include "common.h"

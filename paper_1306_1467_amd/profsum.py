@@ -33,11 +33,19 @@ SCAN_SOURCES = ["paper_1306_1467_amd/csrc/k_scan.hip", "paper_1306_1467_amd/csrc
                 "paper_1306_1467_amd/csrc/round_core.h", "paper_1306_1467_amd/csrc/common.h"]
 
 
+def _code_only(text: str) -> str:
+    """The source without comments and with whitespace collapsed: comment
+    edits leave a counter record valid, code edits do not."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def scan_source_hash() -> str:
     h = hashlib.sha256()
     for p in SCAN_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
