@@ -8,10 +8,14 @@ features, the threshold, beta / alpha and the weight update.  The one-time
 preparation (integral images, feature values, per-feature sort) runs before
 the timed region and is reported separately as init_ms.
 
-Prints one JSON line, which also carries the batched-jobs measurement
-(32 uneven jobs by default, jobs*rounds/s, against the same jobs run one at
-a time through the single-job path) and the FP64 oracle's round time on the
-host cores for a bounded sample of features.
+The scan's launch schedule is the one measured fastest at init (--schedule -1,
+the default) or a fixed one.  Beside the round time the line carries the
+scan's HBM roofline (algorithmic key bytes over its live-measured device
+time, and the copy-calibrated rocprofv3 traffic when it was taken on the same
+code and schedule), a stream probe (the same key reads with no arithmetic),
+the batched-jobs measurement (32 uneven jobs by default, jobs*rounds/s,
+against the same jobs run one at a time through the single-job path) and the
+FP64 oracle's round time on the host cores over 20 of the 200 rounds.
 """
 from __future__ import annotations
 
