@@ -139,6 +139,20 @@ def run_single(args, torch, vb, synth):
     per_round = sorted(evs[r].elapsed_time(evs[r + 1]) for r in range(args.steps))
     pct = lambda q: per_round[min(len(per_round) - 1, int(q * len(per_round)))]
     rec = tr.round()
+    # the strong classifier of 200 stumps on the training windows (outside the timed region)
+    stumps = tr.train(200)
+    tr.classify(stumps)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(tr.stream):
+        c0.record()
+    for _ in range(5):
+        tr.classify(stumps)
+    with torch.cuda.stream(tr.stream):
+        c1.record()
+    tr.stream.synchronize()
+    classify_ms = c0.elapsed_time(c1) / 5
+    correct = int((tr.classify(stumps)[0].cpu().numpy() == labels).sum())
     tr.close()
     # per-kernel device times: the same rounds with HIP events around each
     # kernel on the library's stream (direct launches)
@@ -174,6 +188,8 @@ def run_single(args, torch, vb, synth):
                      "kernel": f"k_scan (schedule {schedule})", "alg_bytes_per_launch": alg_bytes},
         "last_round": {"feature": int(rec.feature), "error_raw": rec.error_raw, "polarity": int(rec.polarity),
                        "threshold": int(rec.threshold)},
+        "strong_classifier": {"stumps": 200, "windows": n, "ms": round(classify_ms, 4),
+                              "training_accuracy": round(correct / n, 4)},
         "stream_probe": {"ms": round(probe_ms, 4), "key_GBps": round(alg_bytes / (probe_ms * 1e-3) / 1e9, 1),
                          "scan_time_over_probe": round(probe_ms / scan_avg, 4)},
         "schedule_tuning": tuning, "schedule": schedule,
@@ -305,6 +321,7 @@ def main():
         "roofline": res["roofline"],
         "last_round": res["last_round"],
         "stream_probe": res["stream_probe"],
+        "strong_classifier": res["strong_classifier"],
         "schedule_tuning": res["schedule_tuning"],
     }
     for name in [c.strip() for c in args.batched.split(",") if c.strip()]:
