@@ -366,3 +366,31 @@ def test_wide_keys_fallback_sort():
         v = vals[a][o.cpu().numpy()[0]]
         assert (np.diff(v) >= 0).all()
     tr.close()
+
+
+@pytest.mark.parametrize("W,H", [(13, 19), (24, 10), (5, 32), (32, 7)])
+def test_rectangular_windows(W, H):
+    """Windows that are not square: integral images, every feature value,
+    the sorted keys and two rounds against the oracle."""
+    rng = np.random.default_rng(1000 + W * 40 + H)
+    n = 700
+    images = (rng.integers(0, 6, size=(n, H, W)) * 51).astype(np.uint8)
+    labels = (rng.random(n) < 0.4).astype(np.uint8)
+    say(f"rectangular windows {W}x{H}")
+    otr = oracle.Trainer(images, labels)
+    tr = _trainer(images, labels)
+    assert tr.F == len(otr.feats) == oracle.feature_count(W, H)
+    assert (tr.integral().cpu().numpy() == otr.ii).all()
+    assert (tr.feature_values().cpu().numpy() == otr.vals).all()
+    order, flags = tr.sorted(0, tr.F)
+    v = np.take_along_axis(otr.vals, order.cpu().numpy(), axis=1)
+    assert (np.diff(v, axis=1) >= 0).all()
+    for t in range(2):
+        wn = otr.w / otr.w.sum()
+        rec, ferr = tr.round(feature_err=True)
+        orec, ost = otr.round()
+        ferr = ferr.cpu().numpy()
+        assert (np.abs(ferr[:, 0] - ost["err_pos"]) <= err_tolerance(ost["err_pos"], n, "fp32_wide")).all()
+        assert (np.abs(ferr[:, 1] - ost["err_neg"]) <= err_tolerance(ost["err_neg"], n, "fp32_wide")).all()
+        check_stump(rec, ost, orec, otr.vals, labels, wn, n, "fp32_wide")
+    tr.close()
