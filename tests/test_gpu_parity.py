@@ -394,3 +394,51 @@ def test_rectangular_windows(W, H):
         assert (np.abs(ferr[:, 1] - ost["err_neg"]) <= err_tolerance(ost["err_neg"], n, "fp32_wide")).all()
         check_stump(rec, ost, orec, otr.vals, labels, wn, n, "fp32_wide")
     tr.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32_wide", "fp64", "fp32_kahan", "fp32"])
+def test_exact_arithmetic_zero_weights_ties(tiny, precision):
+    """Dyadic weights with 30 % zeros: prefix sums repeat across many split
+    ranks, so every tie-break (smaller error, feature, p = +1, smaller rank)
+    decides; with no rounding anywhere both sides must agree bit for bit."""
+    images, labels, otr = tiny
+    n = len(labels)
+    rng = np.random.default_rng(77)
+    k = rng.integers(1, 1001, size=n).astype(np.int64)
+    k[rng.random(n) < 0.3] = 0
+    m = int(np.ceil(np.log2(k.sum())))
+    k[int(np.argmax(k))] += (1 << m) - int(k.sum())
+    w = k.astype(np.float64) / float(1 << m)
+    say(f"exact dyadic weights with zeros, {precision}")
+    tr = _trainer(images, labels, precision=precision)
+    tr.set_weights(w)
+    rec, ferr = tr.round(feature_err=True)
+    ferr = ferr.cpu().numpy()
+    orec, ost = otr.round(weights=w)
+    assert np.array_equal(ferr[:, 0], ost["err_pos"])
+    assert np.array_equal(ferr[:, 1], ost["err_neg"])
+    assert (rec.feature, rec.polarity, rec.threshold, rec.split_rank) == \
+        (orec.feature, orec.polarity, orec.theta, orec.split)
+    assert rec.error_raw == orec.err_raw
+    tr.close()
+
+
+def test_single_positive_window():
+    """One positive among many negatives (l = 1): Table 2 gives it weight 1/2."""
+    images, labels = synth.small_job((210, 0), 400, 10, 4)
+    labels = np.zeros_like(labels)
+    labels[123] = 1
+    say("one positive window")
+    otr = oracle.Trainer(images, labels)
+    tr = _trainer(images, labels)
+    w = tr.weights().cpu().numpy()
+    assert abs(w[123] - 0.5) <= 4e-16 and np.allclose(np.delete(w, 123), 0.5 / 399, rtol=1e-15, atol=0)
+    n = len(labels)
+    for t in range(3):
+        wn = otr.w / otr.w.sum()
+        rec, ferr = tr.round(feature_err=True)
+        orec, ost = otr.round()
+        ferr = ferr.cpu().numpy()
+        assert (np.abs(ferr[:, 0] - ost["err_pos"]) <= err_tolerance(ost["err_pos"], n, "fp32_wide")).all()
+        check_stump(rec, ost, orec, otr.vals, labels, wn, n, "fp32_wide")
+    tr.close()
