@@ -442,3 +442,43 @@ def test_single_positive_window():
         assert (np.abs(ferr[:, 0] - ost["err_pos"]) <= err_tolerance(ost["err_pos"], n, "fp32_wide")).all()
         check_stump(rec, ost, orec, otr.vals, labels, wn, n, "fp32_wide")
     tr.close()
+
+
+def test_identical_windows_every_feature_constant():
+    """Every window the same image: every feature is constant, the only
+    splits are k = 0 and k = n, the best error is exactly 1/2 (beta = 1,
+    alpha = 0) and the tie-break picks p = +1 at k = 0; weights stay put."""
+    # 64 positives and 128 negatives: the Table 2 weights 2^-7 and 2^-8 and
+    # the class sums 1/2 are exact in every precision
+    n = 192
+    images = np.repeat(synth.small_job((220, 0), 1, 12, 8)[0], n, axis=0)
+    labels = np.zeros(n, np.uint8)
+    labels[np.random.default_rng(220).permutation(n)[:64]] = 1
+    tr = _trainer(images, labels)
+    w0 = tr.weights().cpu().numpy()
+    for t in range(2):
+        rec = tr.round()
+        assert rec.error_raw == 0.5 and rec.beta == 1.0 and rec.alpha == 0.0
+        assert (rec.feature, rec.polarity, rec.split_rank) == (0, 1, 0)
+    assert np.allclose(tr.weights().cpu().numpy(), w0, rtol=1e-15, atol=0)
+    tr.close()
+
+
+def test_largest_window_all_types():
+    """32 x 32 windows with all five types (the largest feature set)."""
+    images, labels = synth.small_job((230, 0), 260, 32, 4)
+    say("32x32 windows, all types")
+    otr = oracle.Trainer(images, labels)
+    tr = _trainer(images, labels)
+    assert tr.F == len(otr.feats)
+    assert (tr.feature_values().cpu().numpy() == otr.vals).all()
+    n = len(labels)
+    for t in range(2):
+        wn = otr.w / otr.w.sum()
+        rec, ferr = tr.round(feature_err=True)
+        orec, ost = otr.round()
+        ferr = ferr.cpu().numpy()
+        assert (np.abs(ferr[:, 0] - ost["err_pos"]) <= err_tolerance(ost["err_pos"], n, "fp32_wide")).all()
+        assert (np.abs(ferr[:, 1] - ost["err_neg"]) <= err_tolerance(ost["err_neg"], n, "fp32_wide")).all()
+        check_stump(rec, ost, orec, otr.vals, labels, wn, n, "fp32_wide")
+    tr.close()
