@@ -152,6 +152,7 @@ struct UpdLds {
     double sh[kUpdWg / 64];
     Wt val[kMaxSeg * 8];       // table values of the winning lane's keys, rank order
     uint32_t flags[kMaxSeg];   // run-end flags, one byte per unit
+    double cand[kMaxSeg * 8];  // rounded-sum modes: the lane's candidate values, rank order
     int64_t k;
     int32_t theta;
     int32_t pad;
@@ -311,25 +312,49 @@ __device__ __forceinline__ void update_body(const JobDev& jd, const WgBest* __re
                 k = 8 * lane_start(jd.g, L) + best_r + 1;
             }
         }
-    } else if (tid == 0 && L >= 0) {
-        // rounded running sums: replayed in the scan's order by one thread
-        LaneAcc<PREC> a;
-        decltype(a.add(Wt(0))) ext = pol > 0 ? -4 : 4;
-        int ext_rank = -1;
-        for (int r = 0; r < cntL; ++r) {
-            Wt v8[8];
+    } else if (L >= 0) {
+        // rounded running sums: one thread recomputes the lane's candidate
+        // values in the scan's order (a single dependency chain, no
+        // selection), then the workgroup finds the extreme at a run end and
+        // its first rank
+        if (tid == 0) {
+            LaneAcc<PREC> a;
+            for (int r = 0; r < cntL; ++r) {
+                Wt v8[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v8[e] = lds.val[r * 8 + e];
-            const uint32_t fr = lds.flags[r];
+                for (int e = 0; e < 8; ++e) v8[e] = lds.val[r * 8 + e];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const auto v = a.add(v8[e]);
-                const bool c = ((fr >> e) & 1u) && (pol > 0 ? v > ext : v < ext);
-                ext = c ? v : ext;
-                ext_rank = c ? 8 * r + e : ext_rank;
+                for (int e = 0; e < 8; ++e) lds.cand[r * 8 + e] = (double)a.add(v8[e]);
             }
         }
-        k = 8 * lane_start(jd.g, L) + ext_rank + 1;
+        __syncthreads();
+        double best_v = pol > 0 ? -4.0 : 4.0;
+        int best_r = 0x7FFFFFFF;
+        for (int q = tid; q < cntL * 8; q += kUpdWg) {   // ascending per thread: ties keep the first
+            if ((lds.flags[q >> 3] >> (q & 7)) & 1u) {
+                const double v = lds.cand[q];
+                if (pol > 0 ? v > best_v : v < best_v) { best_v = v; best_r = q; }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o; o >>= 1) {
+            const double ov = __shfl_xor(best_v, o);
+            const int orr = __shfl_xor(best_r, o);
+            const bool c = (pol > 0 ? ov > best_v : ov < best_v) || (ov == best_v && orr < best_r);
+            if (c) { best_v = ov; best_r = orr; }
+        }
+        __syncthreads();
+        if (lane == 0) { lds.wb[wv].eps = best_v; lds.wb[wv].lane = best_r; }
+        __syncthreads();
+        if (tid == 0) {
+            for (int q = 1; q < kUpdWg / 64; ++q) {
+                const double ov = lds.wb[q].eps;
+                const int orr = lds.wb[q].lane;
+                const bool c = (pol > 0 ? ov > best_v : ov < best_v) || (ov == best_v && orr < best_r);
+                if (c) { best_v = ov; best_r = orr; }
+            }
+            k = 8 * lane_start(jd.g, L) + best_r + 1;
+        }
     }
     if (tid == 0) {
         // 3. threshold from the window at the rank just above (p = +1) or at
