@@ -14,7 +14,7 @@
 // that of the single-job kernels, so the stumps equal those of the job run
 // alone.
 #include "batch.h"
-#include "round_core.h"
+#include "update_core.h"
 
 namespace vjb {
 

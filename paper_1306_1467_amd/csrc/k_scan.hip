@@ -1,12 +1,7 @@
-// Per-round kernels of one job.
-//
-// k_scan: every feature's best stump under the current weights (Section 2.3
-// step 2 / Section 3.3.2 step 3a, all features at once) and the first level
-// of the argmin per workgroup.  Normalisation (step 1) happens as each
-// workgroup fills its LDS weight table.
-// k_update: the second level of the argmin, split rank, threshold, beta and
-// alpha (steps 3-4), and the weight update w_i <- w_i beta^(1 - e_i) with
-// per-workgroup partial sums for the next normalisation.
+// Per-round scan kernel of one job: every feature's best stump under the
+// current weights (Section 2.3 step 2 / Section 3.3.2 step 3a, all features
+// at once) and the first level of the argmin per workgroup.  Normalisation
+// (step 1) happens as each workgroup fills its LDS weight table.
 #include "round_core.h"
 
 namespace vjb {
@@ -37,11 +32,6 @@ __global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, false>
     }
     const WgBest b = block_best<NG>(lds.wb, best, LPF);
     if (tid == 0) jd.wgb[blockIdx.x] = b;
-}
-
-template <int PREC>
-__global__ __launch_bounds__(kUpdWg) void k_update(JobDev jd, int n_wg) {
-    update_body<PREC>(jd, jd.wgb, n_wg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -119,20 +109,6 @@ int scan_plan(ScanPlan& p, int precision, bool narrow, int schedule, int64_t n, 
 int scan_launch(const ScanPlan& p, const JobDev& jd, double2* ferr, hipStream_t s) {
     void* args[] = {(void*)&jd, (void*)&ferr};
     VJB_HIP(hipLaunchKernel(p.kernel, dim3(p.grid), dim3(p.wg), args, p.lds, s));
-    return BOOST_OK;
-}
-
-int update_launch(const JobDev& jd, int n_wg, hipStream_t s) {
-    const void* k;
-    switch (jd.precision) {
-    case BOOST_PREC_FP32: k = (const void*)k_update<BOOST_PREC_FP32>; break;
-    case BOOST_PREC_FP32_KAHAN: k = (const void*)k_update<BOOST_PREC_FP32_KAHAN>; break;
-    case BOOST_PREC_FP64: k = (const void*)k_update<BOOST_PREC_FP64>; break;
-    default: k = (const void*)k_update<BOOST_PREC_FP32_WIDE>; break;
-    }
-    JobDev a = jd;
-    void* args[] = {(void*)&a, (void*)&n_wg};
-    VJB_HIP(hipLaunchKernel(k, dim3((unsigned)jd.n_part), dim3(kUpdWg), args, 0, s));
     return BOOST_OK;
 }
 

@@ -47,7 +47,9 @@ int probe_launch(const ScanPlan& p, int schedule, const JobDev& jd, uint32_t* si
 // tune.cpp: measured schedule choice
 constexpr int kTuneReps = 5;        // timed launches per candidate of a single job (the minimum counts)
 constexpr int kTuneRepsBatch = 3;   // the same for a batch (its launches are longer)
-int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, double& best_ms);
+// Runs launch() once untimed (when warm), then `reps` times each bracketed by
+// HIP events on s; best_ms is the fastest.
+int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, double& best_ms, bool warm = true);
 bool tune_cache_get(const std::string& key, std::vector<int>& choice);
 void tune_cache_put(const std::string& key, const std::vector<int>& choice);
 // Times every schedule with the job's lane count; ms_out[k] = -1 for schedules

@@ -14,7 +14,7 @@
 
 namespace vjb {
 
-int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, double& best_ms) {
+int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, double& best_ms, bool warm) {
     hipEvent_t e[2];
     VJB_HIP(hipEventCreate(&e[0]));
     if (hipEventCreate(&e[1]) != hipSuccess) {
@@ -22,7 +22,7 @@ int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, d
         set_error("hipEventCreate failed");
         return BOOST_E_DEVICE;
     }
-    int rc = launch();   // untimed: first-touch and instruction-cache warm-up
+    int rc = warm ? launch() : BOOST_OK;   // untimed: first-touch and instruction-cache warm-up
     best_ms = 1e300;
     for (int r = 0; r < reps && rc == BOOST_OK; ++r) {
         float ms = 0;
@@ -81,16 +81,17 @@ int tune_single(const JobDev& jd, int precision, int num_cu, int device, hipStre
     }
     if (ids.empty()) { set_error("no launch schedule fits this job"); return BOOST_E_INVALID; }
     // candidates are timed in turn, kTuneReps rounds over all of them, so that
-    // slow drifts of the clock do not favour one; each keeps its fastest launch
+    // slow drifts of the clock do not favour one; each keeps its fastest
+    // launch.  Round 0 only warms every candidate up (one untimed launch).
     std::vector<double> best(ids.size(), 1e300);
     int rc;
     for (int rep = 0; rep <= kTuneReps; ++rep)
         for (size_t c = 0; c < ids.size(); ++c) {
             double ms = 0;
-            if ((rc = time_launches(s, rep == 0 ? 0 : 1, [&]() { return scan_launch(plans[c], jd, nullptr, s); }, ms)) !=
-                BOOST_OK)
+            if ((rc = time_launches(s, rep == 0 ? 0 : 1, [&]() { return scan_launch(plans[c], jd, nullptr, s); }, ms,
+                                    rep == 0)) != BOOST_OK)
                 return rc;
-            if (rep > 0 && ms < best[c]) best[c] = ms;   // round 0 only warms up
+            if (rep > 0 && ms < best[c]) best[c] = ms;
         }
     size_t win = 0;
     for (size_t c = 0; c < ids.size(); ++c) {
