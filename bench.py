@@ -13,9 +13,12 @@ the default) or a fixed one.  Beside the round time the line carries the
 scan's HBM roofline (algorithmic key bytes over its live-measured device
 time, and the copy-calibrated rocprofv3 traffic when it was taken on the same
 code and schedule), a stream probe (the same key reads with no arithmetic),
-the batched-jobs measurement (32 uneven jobs by default, jobs*rounds/s,
-against the same jobs run one at a time through the single-job path) and the
-FP64 oracle's round time on the host cores over 20 of the 200 rounds.
+the same workload in the other precision modes (FP32 weights with
+compensated FP32 sums, FP64, plain FP32; per-kernel device times over 50
+rounds), the batched-jobs measurement (32 uneven jobs by default,
+jobs*rounds/s, against the same jobs run one at a time through the
+single-job path) and the FP64 oracle's round time on the host cores over 20
+of the 200 rounds.
 """
 from __future__ import annotations
 
@@ -198,6 +201,31 @@ def run_single(args, torch, vb, synth):
     return out, images, labels
 
 
+def run_precision_sweep(args, torch, vb, images, labels, F: int, n: int):
+    """The same workload in the other precision modes: per-kernel device
+    times (HIP events around each kernel, direct launches) over a few rounds,
+    each under the measured schedule choice."""
+    out = {}
+    modes = [m for m in args.sweep_precisions.split(",") if m and m != args.precision]
+    for prec in modes:
+        tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=prec,
+                        schedule_id=vb.BOOST_SCHEDULE_AUTO, flags=vb.BOOST_FLAG_TIMING)
+        schedule, _ = tr.schedule()
+        vb.boost_train(tr.ctx, 3, False)
+        vb.boost_reset_timing(tr.ctx)
+        recs = vb.boost_train(tr.ctx, args.sweep_rounds, True)
+        tr.stream.synchronize()
+        scan_ms, upd_ms, nr, _ = vb.boost_get_timing(tr.ctx)
+        tr.close()
+        del tr
+        scan_avg = scan_ms / nr
+        out[prec] = {"schedule": schedule, "rounds": nr, "scan_ms_avg": round(scan_avg, 4),
+                     "update_ms_avg": round(upd_ms / nr, 4), "ms_per_round": round((scan_ms + upd_ms) / nr, 4),
+                     "scan_hbm_frac": round(F * n * 2 / (scan_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "last_error_raw": float(recs[-1]["error_raw"])}
+    return out
+
+
 def run_batched(name, args, torch, vb, synth):
     """Jobs of a batched workload trained together (one scan + one update
     launch per round for all jobs) against the same jobs trained one at a
@@ -266,6 +294,9 @@ def main():
     ap.add_argument("--cpu-features", type=int, default=0, help="oracle features (0: all)")
     ap.add_argument("--cpu-rounds", type=int, default=20)
     ap.add_argument("--cpu-rounds-1t", type=int, default=1)
+    ap.add_argument("--sweep-precisions", default="fp32_kahan,fp64,fp32",
+                    help="other precision modes timed on the same workload (empty: none)")
+    ap.add_argument("--sweep-rounds", type=int, default=50)
     ap.add_argument("--batched", default="batch32",
                     help="comma list of batched workloads to measure (batch32: 32 uneven jobs of 24x24 windows, "
                          "batch64: 64 jobs of 16-28 px windows); empty for none")
@@ -324,6 +355,8 @@ def main():
         "strong_classifier": res["strong_classifier"],
         "schedule_tuning": res["schedule_tuning"],
     }
+    if args.sweep_precisions:
+        line["precision_sweep"] = run_precision_sweep(args, torch, vb, images, labels, res["F"], res["n"])
     for name in [c.strip() for c in args.batched.split(",") if c.strip()]:
         line[f"batched_{name}"] = run_batched(name, args, torch, vb, synth)
     if not args.no_cpu_baseline:

@@ -98,18 +98,22 @@ __host__ __device__ inline int64_t mem_to_unit(const KeyGeom& g, int64_t mu) {
 }
 
 // Key encodings of one dword holding ranks 2a (low half) and 2a+1 (high half):
-//  narrow: low = (i0 << 2) | f0 | (f1 << 1), high = (i1 << 2)
+//  narrow: low = (i0 << 2) | c0 | (c1 << 1), high = (i1 << 2)
 //          -> LDS byte offset of a float table is (dword & 0xFFFC) and (dword >> 16)
-//  wide:   low = (i0 << 1) | f0, high = (i1 << 1) | f1
-// f = 1 marks the last rank of a run of equal values (a realisable split after it).
+//  wide:   low = (i0 << 1) | c0, high = (i1 << 1) | c1
+// with c = 1 - f, where f = 1 marks the last rank of a run of equal values (a
+// realisable split after it): the stored bit says "no split here", which the
+// scan turns into its candidate mask with one bit-field extract.
+// encode_pair / decode_pair take and return f.
 __host__ __device__ inline uint32_t encode_pair(int narrow, uint32_t i0, uint32_t f0, uint32_t i1, uint32_t f1) {
-    if (narrow) return (i0 << 2) | f0 | (f1 << 1) | (i1 << 18);
-    return (i0 << 1) | f0 | (((i1 << 1) | f1) << 16);
+    const uint32_t c0 = f0 ^ 1u, c1 = f1 ^ 1u;
+    if (narrow) return (i0 << 2) | c0 | (c1 << 1) | (i1 << 18);
+    return (i0 << 1) | c0 | (((i1 << 1) | c1) << 16);
 }
 __host__ __device__ inline void decode_pair(int narrow, uint32_t d, uint32_t& i0, uint32_t& f0, uint32_t& i1,
                                             uint32_t& f1) {
-    if (narrow) { i0 = (d & 0xFFFF) >> 2; f0 = d & 1; f1 = (d >> 1) & 1; i1 = d >> 18; }
-    else { i0 = (d & 0xFFFF) >> 1; f0 = d & 1; i1 = d >> 17; f1 = (d >> 16) & 1; }
+    if (narrow) { i0 = (d & 0xFFFF) >> 2; f0 = (d & 1) ^ 1u; f1 = ((d >> 1) & 1) ^ 1u; i1 = d >> 18; }
+    else { i0 = (d & 0xFFFF) >> 1; f0 = (d & 1) ^ 1u; i1 = d >> 17; f1 = ((d >> 16) & 1) ^ 1u; }
 }
 
 // A dword of two padding keys (window index n: the zero table entry, no run end).

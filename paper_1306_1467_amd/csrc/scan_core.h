@@ -23,22 +23,20 @@
 
 namespace vjb {
 
-// Masked candidates: a position that is not the end of a run of equal values
-// becomes a quiet NaN, which v_max / v_min ignore (IEEE maxNum / minNum: a
-// quiet NaN operand yields the other operand).  The scan translation unit is
-// built with -fno-honor-nans so that no canonicalisation is inserted around
-// these operations; no NaN ever reaches an arithmetic operation.
-constexpr uint32_t kQNaNHi = 0x7FF80000u;   // high dword of a double quiet NaN
-constexpr uint32_t kQNaN32 = 0x7FC00000u;   // float quiet NaN
-
-__device__ __forceinline__ double with_hi(double v, uint32_t m, uint32_t alt_hi) {
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    const uint32_t hi = ((uint32_t)(b >> 32) & m) | (alt_hi & ~m);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | (uint32_t)b));
+// Masked candidates: at a position that is not the end of a run of equal
+// values the candidate becomes a quiet NaN, which v_max / v_min ignore (IEEE
+// maxNum / minNum: a quiet NaN operand yields the other operand).  The mask
+// is added rather than merged: a candidate is v + z with z = +0 (a split
+// here: v + 0 = v exactly, -0 aside, which compares equal to +0) or z = the
+// all-ones pattern, a quiet NaN (no split: the sum is a quiet NaN).  The
+// addition writes a fresh register (pair), so the running sum needs no copy.
+// The scan translation unit is built with -fno-honor-nans so that no
+// canonicalisation is inserted around the max / min; the only NaN values are
+// these masks and the sums they poison.
+__device__ __forceinline__ double nan_or_zero(uint32_t m) {
+    return __longlong_as_double((long long)((uint64_t)m << 32));
 }
-__device__ __forceinline__ float with_bits(float v, uint32_t m, uint32_t alt) {
-    return __uint_as_float((__float_as_uint(v) & m) | (alt & ~m));
-}
+__device__ __forceinline__ float nan_or_zero32(uint32_t m) { return __uint_as_float(m); }
 
 // Bit b of d as an all-ones / all-zeros mask.
 __device__ __forceinline__ uint32_t bitmask(uint32_t d, int b) {
@@ -52,13 +50,14 @@ template <> struct ScanTypes<BOOST_PREC_FP64>       { using W = double; using A 
 template <> struct ScanTypes<BOOST_PREC_FP32_WIDE>  { using W = float;  using A = double; };
 
 // Per-lane accumulator.  A = type used across lanes and for the final errors.
+// cand(v, m): v is a candidate unless m is all ones (no split at this rank).
 template <int PREC> struct LaneAcc;
 
 template <> struct LaneAcc<BOOST_PREC_FP32> {
     float s = 0.f, mx = -4.f, mn = 4.f;
     __device__ __forceinline__ float add(float w) { s += w; return s; }
     __device__ __forceinline__ void cand(float v, uint32_t m) {
-        const float c = with_bits(v, m, kQNaN32);
+        const float c = v + nan_or_zero32(m);
         mx = fmaxf(mx, c);
         mn = fminf(mn, c);
     }
@@ -84,7 +83,7 @@ template <> struct LaneAcc<BOOST_PREC_FP32_KAHAN> {
         return (double)s + (double)c;
     }
     __device__ __forceinline__ void cand(double v, uint32_t m) {
-        const double x = with_hi(v, m, kQNaNHi);
+        const double x = v + nan_or_zero(m);
         mx = fmax(mx, x);
         mn = fmin(mn, x);
     }
@@ -97,7 +96,7 @@ template <> struct LaneAcc<BOOST_PREC_FP64> {
     double s = 0.0, mx = -4.0, mn = 4.0;
     __device__ __forceinline__ double add(double w) { s += w; return s; }
     __device__ __forceinline__ void cand(double v, uint32_t m) {
-        const double c = with_hi(v, m, kQNaNHi);
+        const double c = v + nan_or_zero(m);
         mx = fmax(mx, c);
         mn = fmin(mn, c);
     }
@@ -110,7 +109,7 @@ template <> struct LaneAcc<BOOST_PREC_FP32_WIDE> {
     double s = 0.0, mx = -4.0, mn = 4.0;
     __device__ __forceinline__ double add(float w) { s += (double)w; return s; }
     __device__ __forceinline__ void cand(double v, uint32_t m) {
-        const double c = with_hi(v, m, kQNaNHi);
+        const double c = v + nan_or_zero(m);
         mx = fmax(mx, c);
         mn = fmin(mn, c);
     }
@@ -140,18 +139,20 @@ __device__ __forceinline__ Wt tab_hi(const Wt* tab, uint32_t d) {
         return *(const Wt*)((const char*)tab + off);
     }
 }
+// All ones where the key in the low / high half of d is not the end of a run
+// (no split after it), zero where it is.
 template <bool NARROW>
-__device__ __forceinline__ uint32_t flag_lo(uint32_t d) { return bitmask(d, 0); }
+__device__ __forceinline__ uint32_t nosplit_lo(uint32_t d) { return bitmask(d, 0); }
 template <bool NARROW>
-__device__ __forceinline__ uint32_t flag_hi(uint32_t d) { return NARROW ? bitmask(d, 1) : bitmask(d, 16); }
+__device__ __forceinline__ uint32_t nosplit_hi(uint32_t d) { return NARROW ? bitmask(d, 1) : bitmask(d, 16); }
 
 template <int PREC, bool NARROW>
 __device__ __forceinline__ void scan_dword(LaneAcc<PREC>& a, const typename ScanTypes<PREC>::W* tab, uint32_t d) {
     using Wt = typename ScanTypes<PREC>::W;
     const Wt w0 = tab_lo<Wt, NARROW>(tab, d);
     const Wt w1 = tab_hi<Wt, NARROW>(tab, d);
-    a.cand(a.add(w0), flag_lo<NARROW>(d));
-    a.cand(a.add(w1), flag_hi<NARROW>(d));
+    a.cand(a.add(w0), nosplit_lo<NARROW>(d));
+    a.cand(a.add(w1), nosplit_hi<NARROW>(d));
 }
 
 template <int PREC, bool NARROW>
