@@ -127,10 +127,14 @@ def counters(fetch_csv: str, write_csv: str, copy_gib: float, kernel: str, preci
 def activity(paths, kernel: str, keys: int, commands, cus: int = 256, simds_per_cu: int = 4, xcds: int = 8) -> str:
     pat = re.compile(kernel)
     agg = {}
+    clocks = []   # GHz per dispatch: busy cycles per XCD over the dispatch's own duration
     for path in paths:
         for r in _dispatches(path):
             if pat.search(r["Kernel_Name"]):
                 agg.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                dt = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                if r["Counter_Name"] == "GRBM_GUI_ACTIVE" and dt > 0:
+                    clocks.append(float(r["Counter_Value"]) / xcds / dt)
     m = {k: statistics.mean(v) for k, v in agg.items()}
     lines = [f"# Unit activity of `{kernel}` (rocprofv3 counters, mean per launch)", ""]
     for c in commands:
@@ -143,6 +147,9 @@ def activity(paths, kernel: str, keys: int, commands, cus: int = 256, simds_per_
     if "GRBM_GUI_ACTIVE" in m:
         cyc = m["GRBM_GUI_ACTIVE"] / xcds   # GRBM_GUI_ACTIVE is summed over the XCDs
         lines.append(f"- GPU-busy cycles per XCD: {cyc:,.0f}")
+        if clocks:
+            lines.append(f"- Clock (busy cycles per XCD / dispatch duration, median over dispatches): "
+                         f"{statistics.median(clocks):.2f} GHz")
         if "SQ_INSTS_VALU" in m:
             lines.append(f"- VALU instructions per key (wave-wide): {m['SQ_INSTS_VALU'] / slots:.2f}")
             busy = m["SQ_INSTS_VALU"] * 4.0 / (cus * simds_per_cu) / cyc
