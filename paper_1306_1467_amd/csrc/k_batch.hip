@@ -21,7 +21,7 @@ namespace vjb {
 // One launch per key format: NARROW selects the 14-bit-key jobs (64 KiB
 // table, two workgroups per compute unit) or the 15-bit ones (128 KiB).
 // Segments [s_begin, s_end) belong to this launch; the counter counts from 0.
-template <int PREC, bool NARROW, int WG, int UNROLL, int LPF>
+template <int PREC, bool NARROW, int WG, int UNROLL, int LPF, bool RING>
 __global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, true>::waves_per_eu)) void k_scan_batch(
     const JobDev* __restrict__ jobs, const BatchSeg* __restrict__ segs, uint32_t* __restrict__ next_seg, int s_begin,
     int s_end, const int32_t* __restrict__ job_seg, WgBest* __restrict__ seg_best) {
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, true>:
                 }
                 cur_job = sg.job;
             }
-            best = scan_range<PREC, NARROW, UNROLL, LPF>(jd, tab, sg.f0, sg.f1, wv, WG / 64, tp, tn, nullptr);
+            best = scan_range<PREC, NARROW, UNROLL, LPF, RING>(jd, tab, sg.f0, sg.f1, wv, WG / 64, tp, tn, nullptr);
         }
         const WgBest b = block_best<NG>(lds.wb, best, LPF);
         if (tid == 0) seg_best[s] = b;
@@ -86,15 +86,16 @@ __global__ void k_gather_records(const JobDev* __restrict__ jobs, int n_jobs, in
 template <int PREC, bool NARROW>
 static const void* batch_kernel_ptr(int schedule) {
     switch (schedule) {
-    case 1: return (const void*)k_scan_batch<PREC, NARROW, 512, 10, 16>;
-    case 2: return (const void*)k_scan_batch<PREC, NARROW, 512, 6, 16>;
-    case 3: return (const void*)k_scan_batch<PREC, NARROW, 512, 4, 16>;
-    case 4: return (const void*)k_scan_batch<PREC, NARROW, 1024, 8, 16>;
-    case 5: return (const void*)k_scan_batch<PREC, NARROW, 512, 8, 32>;
-    case 6: return (const void*)k_scan_batch<PREC, NARROW, 512, 10, 64>;
-    case 7: return (const void*)k_scan_batch<PREC, NARROW, 256, 8, 16>;
-    case 8: return (const void*)k_scan_batch<PREC, NARROW, 1024, 4, 16>;
-    default: return (const void*)k_scan_batch<PREC, NARROW, 512, 8, 16>;
+    case 1: return (const void*)k_scan_batch<PREC, NARROW, 512, 10, 16, false>;
+    case 2: return (const void*)k_scan_batch<PREC, NARROW, 512, 6, 16, false>;
+    case 3: return (const void*)k_scan_batch<PREC, NARROW, 512, 4, 16, false>;
+    case 4: return (const void*)k_scan_batch<PREC, NARROW, 1024, 8, 16, false>;
+    case 5: return (const void*)k_scan_batch<PREC, NARROW, 512, 8, 32, false>;
+    case 6: return (const void*)k_scan_batch<PREC, NARROW, 512, 10, 64, false>;
+    case 7: return (const void*)k_scan_batch<PREC, NARROW, 256, 8, 16, false>;
+    case 8: return (const void*)k_scan_batch<PREC, NARROW, 1024, 4, 16, false>;
+    case 9: return (const void*)k_scan_batch<PREC, NARROW, 512, 4, 16, true>;
+    default: return (const void*)k_scan_batch<PREC, NARROW, 512, 8, 16, false>;
     }
 }
 

@@ -10,7 +10,7 @@ namespace vjb {
 // Persistent: every workgroup fills its LDS weight table once, then its waves
 // take group-steps of features; each workgroup leaves its best candidate
 // (the first level of the argmin).
-template <int PREC, bool NARROW, int WG, int UNROLL, int LPF>
+template <int PREC, bool NARROW, int WG, int UNROLL, int LPF, bool RING>
 __global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, false>::waves_per_eu)) void k_scan(JobDev jd, double2* __restrict__ ferr) {
     using Wt = typename ScanTypes<PREC>::W;
     constexpr int NG = (WG / 64) * (64 / LPF);
@@ -27,34 +27,36 @@ __global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, false>
             jd.st->sum_w = S; jd.st->t_pos = tp; jd.st->t_neg = tn; jd.st->cur = par;
         }
         const int64_t total_waves = (int64_t)gridDim.x * (WG / 64);
-        best = scan_range<PREC, NARROW, UNROLL, LPF>(jd, tab, 0, jd.F, (int64_t)blockIdx.x * (WG / 64) + wv,
-                                                     total_waves, tp, tn, ferr);
+        best = scan_range<PREC, NARROW, UNROLL, LPF, RING>(jd, tab, 0, jd.F, (int64_t)blockIdx.x * (WG / 64) + wv,
+                                                           total_waves, tp, tn, ferr);
     }
     const WgBest b = block_best<NG>(lds.wb, best, LPF);
     if (tid == 0) jd.wgb[blockIdx.x] = b;
 }
 
 // ---------------------------------------------------------------- launchers
-// Launch schedules: workgroup size, units per batch, lanes per feature.
-struct Schedule { int wg, unroll, lanes; };
+// Launch schedules: workgroup size, units per batch (or register slots of the
+// rotating loads), lanes per feature, rotating loads.
+struct Schedule { int wg, unroll, lanes; bool ring; };
 static const Schedule kSchedules[] = {
-    {512, 8, 16}, {512, 10, 16}, {512, 6, 16}, {512, 4, 16}, {1024, 8, 16}, {512, 8, 32}, {512, 10, 64}, {256, 8, 16},
-    {1024, 4, 16},
+    {512, 8, 16, false}, {512, 10, 16, false}, {512, 6, 16, false}, {512, 4, 16, false}, {1024, 8, 16, false},
+    {512, 8, 32, false}, {512, 10, 64, false}, {256, 8, 16, false}, {1024, 4, 16, false}, {512, 4, 16, true},
 };
 constexpr int kNumSchedules = (int)(sizeof(kSchedules) / sizeof(kSchedules[0]));
 
 template <int PREC, bool NARROW>
 static const void* scan_kernel_ptr(int schedule) {
     switch (schedule) {
-    case 1: return (const void*)k_scan<PREC, NARROW, 512, 10, 16>;
-    case 2: return (const void*)k_scan<PREC, NARROW, 512, 6, 16>;
-    case 3: return (const void*)k_scan<PREC, NARROW, 512, 4, 16>;
-    case 4: return (const void*)k_scan<PREC, NARROW, 1024, 8, 16>;
-    case 5: return (const void*)k_scan<PREC, NARROW, 512, 8, 32>;
-    case 6: return (const void*)k_scan<PREC, NARROW, 512, 10, 64>;
-    case 7: return (const void*)k_scan<PREC, NARROW, 256, 8, 16>;
-    case 8: return (const void*)k_scan<PREC, NARROW, 1024, 4, 16>;
-    default: return (const void*)k_scan<PREC, NARROW, 512, 8, 16>;
+    case 1: return (const void*)k_scan<PREC, NARROW, 512, 10, 16, false>;
+    case 2: return (const void*)k_scan<PREC, NARROW, 512, 6, 16, false>;
+    case 3: return (const void*)k_scan<PREC, NARROW, 512, 4, 16, false>;
+    case 4: return (const void*)k_scan<PREC, NARROW, 1024, 8, 16, false>;
+    case 5: return (const void*)k_scan<PREC, NARROW, 512, 8, 32, false>;
+    case 6: return (const void*)k_scan<PREC, NARROW, 512, 10, 64, false>;
+    case 7: return (const void*)k_scan<PREC, NARROW, 256, 8, 16, false>;
+    case 8: return (const void*)k_scan<PREC, NARROW, 1024, 4, 16, false>;
+    case 9: return (const void*)k_scan<PREC, NARROW, 512, 4, 16, true>;
+    default: return (const void*)k_scan<PREC, NARROW, 512, 8, 16, false>;
     }
 }
 

@@ -48,13 +48,21 @@ __device__ __forceinline__ bool better(const WgBest& c, const WgBest& b) {
 // groups of LPF lanes take one feature each, the g-th group-step of the
 // calling wave handles features f0 + (step0 + g * nsteps) * G + group.
 // Returns this lane's best candidate (the same in every lane of a group).
-template <int PREC, bool NARROW, int UNROLL, int LPF>
+//
+// Two load disciplines.  Batched (RING = false): a lane loads UNROLL units,
+// scans them, then loads the next UNROLL; the next feature's first batch is
+// loaded before the current feature's epilogue.  Rotating (RING = true): each
+// of the UNROLL register slots is reloaded as soon as its unit is scanned,
+// with the unit one batch later -- across feature boundaries too -- so a
+// lane keeps UNROLL units in flight all the time at no register cost; lanes
+// then scan a whole number of batches per feature (the last one padded).
+template <int PREC, bool NARROW, int UNROLL, int LPF, bool RING = false>
 __device__ __forceinline__ WgBest scan_range(const JobDev& jd, const typename ScanTypes<PREC>::W* tab, int64_t f0,
                                              int64_t f1, int64_t step0, int64_t nsteps, double tp, double tn,
                                              double2* __restrict__ ferr) {
     constexpr int G = 64 / LPF;
     constexpr int H = UNROLL / 2;
-    static_assert(UNROLL % 2 == 0, "the tail batch is half a batch");
+    static_assert(RING || UNROLL % 2 == 0, "the tail batch is half a batch");
     const int lane = threadIdx.x & 63;
     const int grp = lane / LPF, L = lane % LPF;
     const int cnt = jd.g.q + (L < jd.g.rem ? 1 : 0);
@@ -77,9 +85,73 @@ __device__ __forceinline__ WgBest scan_range(const JobDev& jd, const typename Sc
     int64_t t = step0;
     int64_t j = f0 + t * G + grp;
     if (f0 + t * G >= f1) return best;
+    uint4 u[UNROLL];
+    if constexpr (RING) {
+        // The scan stream consumes the slots in order; the fill stream runs
+        // one batch ahead: (tf, rr) = feature step and first unit of the
+        // next batch to load, pf / cf = that feature's row and this lane's
+        // unit count (0 past f1: the padding unit is read instead).
+        const int nbr = (per + UNROLL - 1) / UNROLL;
+        int64_t tf = t;
+        int rr = 0;
+        const uint4* pf = jd.keys + j * jd.g.row_units + L;
+        int cf = j < f1 ? cnt : 0;
+        bool fill_full = f0 + tf * G + G - 1 < f1;   // every group of the wave has a feature
+        bool fill_live = true;                        // some group has
+        auto advance_fill = [&]() {
+            rr += UNROLL;
+            if (rr >= nbr * UNROLL) {
+                rr = 0;
+                tf += nsteps;
+                fill_live = f0 + tf * G < f1;
+                fill_full = f0 + tf * G + G - 1 < f1;
+                const int64_t jf = f0 + tf * G + grp;
+                cf = jf < f1 ? cnt : 0;
+                pf = jd.keys + (jf < f1 ? jf : 0) * jd.g.row_units + L;
+            }
+        };
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) u[k] = ld_stream(k < cf ? pf + k * LPF : jd.pad);
+        advance_fill();
+        while (true) {
+            LaneAcc<PREC> a;
+            for (int b = 0; b < nbr; ++b) {
+                if (fill_full && rr + UNROLL <= per - 1) {
+                    // every lane owns units rr .. rr + UNROLL - 1 (each owns at least per - 1)
+                    const uint4* base = pf + rr * LPF;
+#pragma unroll
+                    for (int k = 0; k < UNROLL; ++k) {
+                        scan_unit<PREC, NARROW>(a, tab, u[k]);
+                        u[k] = ld_stream(base + k * LPF);
+                    }
+                } else if (fill_live) {
+#pragma unroll
+                    for (int k = 0; k < UNROLL; ++k) {
+                        scan_unit<PREC, NARROW>(a, tab, u[k]);
+                        const int r = rr + k;
+                        u[k] = ld_stream(r < cf ? pf + r * LPF : jd.pad);
+                    }
+                } else {   // nothing left to load: the wave's last batch
+#pragma unroll
+                    for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
+                }
+                advance_fill();
+            }
+            const FeatureScan fs = finish_feature<PREC, LPF>(a, lane, tp, tn);
+            if (j < f1) {
+                if (ferr != nullptr && L == 0) ferr[j] = make_double2(fs.e_pos, fs.e_neg);
+                const bool pos = fs.e_pos <= fs.e_neg;
+                const double e = pos ? fs.e_pos : fs.e_neg;
+                if (e < best.eps) best = WgBest{e, j, pos ? 1 : -1, pos ? fs.lane_pos : fs.lane_neg};
+            }
+            t += nsteps;
+            if (f0 + t * G >= f1) break;
+            j = f0 + t * G + grp;
+        }
+        return best;
+    }
     // batch 0 of the next feature is loaded before the current feature's
     // group epilogue, so loads stay in flight across features
-    uint4 u[UNROLL];
     int stride;
     const uint4* p = row_of(j, stride);
     load_batch<UNROLL>(u, p, stride, 0, nb, stride ? cnt : 0, jd.pad);

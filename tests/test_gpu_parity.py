@@ -320,6 +320,62 @@ def test_schedules_agree():
         tr.close()
 
 
+# Schedule 9 scans with rotating loads: lanes scan a whole number of 4-unit
+# batches per feature (padding units add zero and hold no split) and the
+# loads run one batch ahead across feature boundaries.  Shapes: one key unit
+# per lane or less, exactly one batch, one unit past it, many batches with
+# remainder lanes, feature counts far below one workgroup step (empty groups
+# and waves), and 15-bit keys.
+ROTATING = 9
+
+
+@pytest.mark.parametrize("seed,n,size,levels", [
+    (0, 2, 4, 2),         # per = 1: the fill stream moves to the next feature at once
+    (1, 37, 6, 3),        # per = 1, ragged units
+    (2, 512, 8, 4),       # per = 4: exactly one batch
+    (3, 513, 8, 256),     # per = 5: one unit past a batch
+    (4, 4099, 6, 16),     # many batches, remainder lanes
+    (5, 300, 3, 4),       # 3x3 windows: fewer features than one workgroup step
+    (6, 16500, 5, 64),    # 15-bit keys
+])
+def test_rotating_loads_match_batched(seed, n, size, levels):
+    images, labels = _tiny(seed, n, size, levels)
+    say(f"rotating loads: seed={seed} n={n} size={size}")
+    assert vb.boost_schedule_count() > ROTATING
+    precisions = ["fp32_wide", "fp32_kahan", "fp32"] + (["fp64"] if n <= 20000 else [])
+    for precision in precisions:
+        ref = _trainer(images, labels, precision=precision, schedule_id=0)
+        a = ref.train(5)
+        wa = ref.weights().cpu().numpy()
+        ref.close()
+        tr = _trainer(images, labels, precision=precision, schedule_id=ROTATING)
+        b = tr.train(5)
+        wb = tr.weights().cpu().numpy()
+        tr.close()
+        assert b.tobytes() == a.tobytes(), precision
+        assert np.array_equal(wb, wa), precision
+
+
+def test_rotating_loads_against_oracle(tiny):
+    images, labels, otr = tiny
+    say("tiny: rotating loads, per-feature errors against the oracle")
+    n = len(labels)
+    tr = _trainer(images, labels, schedule_id=ROTATING)
+    w = synth.random_weights((202, 0), n, -8, 0)
+    for t in range(3):
+        wn = w / w.sum()
+        tr.set_weights(wn)
+        rec, ferr = tr.round(feature_err=True)
+        ferr = ferr.cpu().numpy()
+        otr.w = w.copy()
+        orec, ost = otr.round()
+        assert (np.abs(ferr[:, 0] - ost["err_pos"]) <= err_tolerance(ost["err_pos"], n, "fp32_wide")).all()
+        assert (np.abs(ferr[:, 1] - ost["err_neg"]) <= err_tolerance(ost["err_neg"], n, "fp32_wide")).all()
+        check_stump(rec, ost, orec, otr.vals, labels, wn, n, "fp32_wide")
+        w = otr.w.copy()
+    tr.close()
+
+
 def test_strong_classifier_matches_oracle(tiny):
     images, labels, _ = tiny
     say("strong classifier")
