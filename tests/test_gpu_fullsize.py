@@ -32,11 +32,15 @@ def faces15k():
     return images, labels
 
 
-def test_fullsize_sampled_rounds(faces15k):
+# the tuner's choice is the configuration bench.py times (schedule 9, rotating
+# loads, on the boxes measured); schedule 0 is the batched-load default
+@pytest.mark.parametrize("schedule", [-1, 0])
+def test_fullsize_sampled_rounds(faces15k, schedule):
     images, labels = faces15k
     n = len(labels)
-    say("full size: GPU init (all features)")
-    tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision="fp32_wide")
+    say(f"full size: GPU init (all features), schedule {schedule}")
+    tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision="fp32_wide", schedule_id=schedule)
+    say(f"schedule in use: {tr.schedule()[0]}")
     F = tr.F
     assert F == 162336
     rng = np.random.default_rng(11)
