@@ -19,6 +19,11 @@ __global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, false>
     const int tid = threadIdx.x, wv = tid >> 6;
     WgBest best{DBL_MAX, -1, 0, -1};
     if (!jd.st->stopped) {
+        // rotating loads: the first key loads are issued before the table
+        // fill, so HBM is busy while the workgroup builds its table
+        RingScan<PREC, NARROW, UNROLL, LPF> rs;
+        if constexpr (RING)
+            rs.prime(jd, 0, jd.F, (int64_t)blockIdx.x * (WG / 64) + wv, (int64_t)gridDim.x * (WG / 64));
         const int par = jd.st->wpar;
         const double S = weight_sum(jd);
         double tp, tn;
@@ -27,8 +32,11 @@ __global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, false>
             jd.st->sum_w = S; jd.st->t_pos = tp; jd.st->t_neg = tn; jd.st->cur = par;
         }
         const int64_t total_waves = (int64_t)gridDim.x * (WG / 64);
-        best = scan_range<PREC, NARROW, UNROLL, LPF, RING>(jd, tab, 0, jd.F, (int64_t)blockIdx.x * (WG / 64) + wv,
-                                                           total_waves, tp, tn, ferr);
+        if constexpr (RING)
+            best = rs.run(jd, tab, tp, tn, ferr);
+        else
+            best = scan_range<PREC, NARROW, UNROLL, LPF>(jd, tab, 0, jd.F, (int64_t)blockIdx.x * (WG / 64) + wv,
+                                                         total_waves, tp, tn, ferr);
     }
     const WgBest b = block_best<NG>(lds.wb, best, LPF);
     if (tid == 0) jd.wgb[blockIdx.x] = b;

@@ -44,6 +44,101 @@ __device__ __forceinline__ bool better(const WgBest& c, const WgBest& b) {
     return c.feature >= 0 && (b.feature < 0 || c.eps < b.eps || (c.eps == b.eps && c.feature < b.feature));
 }
 
+// Rotating-load scan of one wave over features [f0, f1) (the RING
+// discipline of scan_range).  The scan stream consumes the UNROLL register
+// slots in order; the fill stream runs one batch ahead: (tf, rr) = feature
+// step and first unit of the next batch to load, pf / cf = that feature's
+// row and this lane's unit count there (0 past f1: the padding unit is read
+// instead).  prime() issues the first loads and may run before the LDS table
+// is filled; run() needs the table.
+template <int PREC, bool NARROW, int UNROLL, int LPF>
+struct RingScan {
+    static constexpr int G = 64 / LPF;
+    uint4 u[UNROLL];
+    int64_t f0, f1, nsteps, t, j, tf;
+    int L, grp, cnt, per, nbr, rr, cf;
+    const uint4* pf;
+    bool any, fill_full, fill_live;
+
+    __device__ __forceinline__ void prime(const JobDev& jd, int64_t f0_, int64_t f1_, int64_t step0,
+                                          int64_t nsteps_) {
+        f0 = f0_; f1 = f1_; nsteps = nsteps_;
+        const int lane = threadIdx.x & 63;
+        grp = lane / LPF; L = lane % LPF;
+        cnt = jd.g.q + (L < jd.g.rem ? 1 : 0);
+        per = jd.g.q + (jd.g.rem > 0 ? 1 : 0);
+        nbr = (per + UNROLL - 1) / UNROLL;
+        t = step0;
+        j = f0 + t * G + grp;
+        any = f0 + t * G < f1;
+        if (!any) return;
+        tf = t;
+        rr = 0;
+        pf = jd.keys + (j < f1 ? j : 0) * jd.g.row_units + L;
+        cf = j < f1 ? cnt : 0;
+        fill_full = f0 + tf * G + G - 1 < f1;   // every group of the wave has a feature
+        fill_live = true;                        // some group has
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) u[k] = ld_stream(k < cf ? pf + k * LPF : jd.pad);
+        advance_fill(jd);
+    }
+
+    __device__ __forceinline__ void advance_fill(const JobDev& jd) {
+        rr += UNROLL;
+        if (rr >= nbr * UNROLL) {
+            rr = 0;
+            tf += nsteps;
+            fill_live = f0 + tf * G < f1;
+            fill_full = f0 + tf * G + G - 1 < f1;
+            const int64_t jf = f0 + tf * G + grp;
+            cf = jf < f1 ? cnt : 0;
+            pf = jd.keys + (jf < f1 ? jf : 0) * jd.g.row_units + L;
+        }
+    }
+
+    __device__ __forceinline__ WgBest run(const JobDev& jd, const typename ScanTypes<PREC>::W* tab, double tp,
+                                          double tn, double2* __restrict__ ferr) {
+        WgBest best{DBL_MAX, -1, 0, -1};
+        if (!any) return best;
+        while (true) {
+            LaneAcc<PREC> a;
+            for (int b = 0; b < nbr; ++b) {
+                if (fill_full && rr + UNROLL <= per - 1) {
+                    // every lane owns units rr .. rr + UNROLL - 1 (each owns at least per - 1)
+                    const uint4* base = pf + rr * LPF;
+#pragma unroll
+                    for (int k = 0; k < UNROLL; ++k) {
+                        scan_unit<PREC, NARROW>(a, tab, u[k]);
+                        u[k] = ld_stream(base + k * LPF);
+                    }
+                } else if (fill_live) {
+#pragma unroll
+                    for (int k = 0; k < UNROLL; ++k) {
+                        scan_unit<PREC, NARROW>(a, tab, u[k]);
+                        const int r = rr + k;
+                        u[k] = ld_stream(r < cf ? pf + r * LPF : jd.pad);
+                    }
+                } else {   // nothing left to load: the wave's last batch
+#pragma unroll
+                    for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
+                }
+                advance_fill(jd);
+            }
+            const FeatureScan fs = finish_feature<PREC, LPF>(a, threadIdx.x & 63, tp, tn);
+            if (j < f1) {
+                if (ferr != nullptr && L == 0) ferr[j] = make_double2(fs.e_pos, fs.e_neg);
+                const bool pos = fs.e_pos <= fs.e_neg;
+                const double e = pos ? fs.e_pos : fs.e_neg;
+                if (e < best.eps) best = WgBest{e, j, pos ? 1 : -1, pos ? fs.lane_pos : fs.lane_neg};
+            }
+            t += nsteps;
+            if (f0 + t * G >= f1) break;
+            j = f0 + t * G + grp;
+        }
+        return best;
+    }
+};
+
 // Scans features [f0, f1) of one job with the LDS table `tab` already filled:
 // groups of LPF lanes take one feature each, the g-th group-step of the
 // calling wave handles features f0 + (step0 + g * nsteps) * G + group.
@@ -85,71 +180,12 @@ __device__ __forceinline__ WgBest scan_range(const JobDev& jd, const typename Sc
     int64_t t = step0;
     int64_t j = f0 + t * G + grp;
     if (f0 + t * G >= f1) return best;
-    uint4 u[UNROLL];
     if constexpr (RING) {
-        // The scan stream consumes the slots in order; the fill stream runs
-        // one batch ahead: (tf, rr) = feature step and first unit of the
-        // next batch to load, pf / cf = that feature's row and this lane's
-        // unit count (0 past f1: the padding unit is read instead).
-        const int nbr = (per + UNROLL - 1) / UNROLL;
-        int64_t tf = t;
-        int rr = 0;
-        const uint4* pf = jd.keys + j * jd.g.row_units + L;
-        int cf = j < f1 ? cnt : 0;
-        bool fill_full = f0 + tf * G + G - 1 < f1;   // every group of the wave has a feature
-        bool fill_live = true;                        // some group has
-        auto advance_fill = [&]() {
-            rr += UNROLL;
-            if (rr >= nbr * UNROLL) {
-                rr = 0;
-                tf += nsteps;
-                fill_live = f0 + tf * G < f1;
-                fill_full = f0 + tf * G + G - 1 < f1;
-                const int64_t jf = f0 + tf * G + grp;
-                cf = jf < f1 ? cnt : 0;
-                pf = jd.keys + (jf < f1 ? jf : 0) * jd.g.row_units + L;
-            }
-        };
-#pragma unroll
-        for (int k = 0; k < UNROLL; ++k) u[k] = ld_stream(k < cf ? pf + k * LPF : jd.pad);
-        advance_fill();
-        while (true) {
-            LaneAcc<PREC> a;
-            for (int b = 0; b < nbr; ++b) {
-                if (fill_full && rr + UNROLL <= per - 1) {
-                    // every lane owns units rr .. rr + UNROLL - 1 (each owns at least per - 1)
-                    const uint4* base = pf + rr * LPF;
-#pragma unroll
-                    for (int k = 0; k < UNROLL; ++k) {
-                        scan_unit<PREC, NARROW>(a, tab, u[k]);
-                        u[k] = ld_stream(base + k * LPF);
-                    }
-                } else if (fill_live) {
-#pragma unroll
-                    for (int k = 0; k < UNROLL; ++k) {
-                        scan_unit<PREC, NARROW>(a, tab, u[k]);
-                        const int r = rr + k;
-                        u[k] = ld_stream(r < cf ? pf + r * LPF : jd.pad);
-                    }
-                } else {   // nothing left to load: the wave's last batch
-#pragma unroll
-                    for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
-                }
-                advance_fill();
-            }
-            const FeatureScan fs = finish_feature<PREC, LPF>(a, lane, tp, tn);
-            if (j < f1) {
-                if (ferr != nullptr && L == 0) ferr[j] = make_double2(fs.e_pos, fs.e_neg);
-                const bool pos = fs.e_pos <= fs.e_neg;
-                const double e = pos ? fs.e_pos : fs.e_neg;
-                if (e < best.eps) best = WgBest{e, j, pos ? 1 : -1, pos ? fs.lane_pos : fs.lane_neg};
-            }
-            t += nsteps;
-            if (f0 + t * G >= f1) break;
-            j = f0 + t * G + grp;
-        }
-        return best;
+        RingScan<PREC, NARROW, UNROLL, LPF> rs;
+        rs.prime(jd, f0, f1, step0, nsteps);
+        return rs.run(jd, tab, tp, tn, ferr);
     }
+    uint4 u[UNROLL];
     // batch 0 of the next feature is loaded before the current feature's
     // group epilogue, so loads stay in flight across features
     int stride;
