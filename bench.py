@@ -308,7 +308,7 @@ def main():
                     help="run one device copy of this many GiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+        print("bench.py: vjboost runs on one GPU only; multi-GPU runs are not supported "
               "(the path would shard features across GPUs: each scans its share and one all-reduce-min "
               "picks the stump)", file=sys.stderr)
         sys.exit(2)
