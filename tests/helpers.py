@@ -12,19 +12,18 @@ def err_tolerance(ref: np.ndarray, n: int, precision: str, keys_per_lane: int = 
 
     The oracle's own FP64 prefix sums carry at most ~2n u64 absolute error
     (weights sum to 1), so every bound has that floor.
-      fp64, fp32_wide: 1e-6 relative (the target tolerance) + floor.
-      fp32_kahan: each candidate is the compensated prefix rounded to FP32,
-        relative 2^-24 of the lane-local prefix, whose magnitude is at most the
-        lane's keys times the largest weight (bounded by 1 here) + 1e-6 relative.
+      fp64, fp32_wide, fp32_kahan: 1e-6 relative + floor.  The compensated
+        mode evaluates each candidate as s + c in FP64 (exact for two floats)
+        and its two-sum carries the prefix to about u32^2, so, as with FP64
+        sums of the FP32 weights, the error left is the FP32 rounding of each
+        weight: at most 2^-24 relative on every error.
       fp32: recursive FP32 summation over a lane segment and the 64-lane scan:
-        (keys_per_lane + 64) u32 (plain FP32, no accuracy target).
+        (keys_per_lane + 64) u32 absolute (plain FP32 meets no relative bound).
     """
     ref = np.abs(np.asarray(ref, dtype=np.float64))
     floor = 4.0 * n * U64
-    if precision in ("fp64", "fp32_wide"):
+    if precision in ("fp64", "fp32_wide", "fp32_kahan"):
         return 1e-6 * ref + floor
-    if precision == "fp32_kahan":
-        return 1e-6 * ref + 4.0 * U32 + floor
     return np.full_like(ref, 2.0 * (keys_per_lane + 64) * U32 + floor)
 
 

@@ -14,7 +14,7 @@ B. A job that is not separable (1,650 windows of contrast 60 with 8 % of the
    chosen stump are compared (30 rounds).
 
 Each mode prints one REPORT line (JSON) with the per-round maxima.  The
-target bar -- per-feature errors within 1e-6 relative, the stump equal
+bar -- per-feature errors within 1e-6 relative, the stump equal
 wherever the oracle's top-two errors differ by more than that -- is asserted
 for FP64, FP32-with-FP64-accumulation and the compensated mode; plain FP32 is
 reported only (it is the configuration the compensated sums exist to fix).
