@@ -91,7 +91,9 @@ typedef struct {
  * eps_floor: > 0 and < 0.5 (default 1e-10).
  * schedule_id: 0 picks the default launch shape (512-thread workgroups, 8
  *   key units per load batch, 16 lanes per feature); 1 .. count-1 select
- *   other shapes (see boost_schedule_count); BOOST_SCHEDULE_AUTO lets init
+ *   other shapes (see boost_schedule_count), among them 9, which keeps 4
+ *   key units per lane in flight all the time (rotating loads, the fastest
+ *   single-job scan measured); BOOST_SCHEDULE_AUTO lets init
  *   time every shape that shares the default's 16-lane key layout on the
  *   job's own keys and keep the fastest (batches: per key format, then also
  *   the work-queue granularity).  Choices are cached per process by workload
