@@ -22,7 +22,7 @@ namespace vjb {
 // table, two workgroups per compute unit) or the 15-bit ones (128 KiB).
 // Segments [s_begin, s_end) belong to this launch; the counter counts from 0.
 template <int PREC, bool NARROW, int WG, int UNROLL, int LPF, bool RING>
-__global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, true>::waves_per_eu)) void k_scan_batch(
+__global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, true, RING>::waves_per_eu)) void k_scan_batch(
     const JobDev* __restrict__ jobs, const BatchSeg* __restrict__ segs, uint32_t* __restrict__ next_seg, int s_begin,
     int s_end, const int32_t* __restrict__ job_seg, WgBest* __restrict__ seg_best) {
     using Wt = typename ScanTypes<PREC>::W;
@@ -95,6 +95,7 @@ static const void* batch_kernel_ptr(int schedule) {
     case 7: return (const void*)k_scan_batch<PREC, NARROW, 256, 8, 16, false>;
     case 8: return (const void*)k_scan_batch<PREC, NARROW, 1024, 4, 16, false>;
     case 9: return (const void*)k_scan_batch<PREC, NARROW, 512, 4, 16, true>;
+    case 10: return (const void*)k_scan_batch<PREC, NARROW, 1024, 4, 16, true>;
     default: return (const void*)k_scan_batch<PREC, NARROW, 512, 8, 16, false>;
     }
 }

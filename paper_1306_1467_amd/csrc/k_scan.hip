@@ -11,7 +11,7 @@ namespace vjb {
 // take group-steps of features; each workgroup leaves its best candidate
 // (the first level of the argmin).
 template <int PREC, bool NARROW, int WG, int UNROLL, int LPF, bool RING>
-__global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, false>::waves_per_eu)) void k_scan(JobDev jd, double2* __restrict__ ferr) {
+__global__ __launch_bounds__(WG, (ScanOccupancy<PREC, NARROW, WG, UNROLL, false, RING>::waves_per_eu)) void k_scan(JobDev jd, double2* __restrict__ ferr) {
     using Wt = typename ScanTypes<PREC>::W;
     constexpr int NG = (WG / 64) * (64 / LPF);
     __shared__ ScanLds<Wt, TabCap<PREC, NARROW>::value, NG> lds;
@@ -49,6 +49,7 @@ struct Schedule { int wg, unroll, lanes; bool ring; };
 static const Schedule kSchedules[] = {
     {512, 8, 16, false}, {512, 10, 16, false}, {512, 6, 16, false}, {512, 4, 16, false}, {1024, 8, 16, false},
     {512, 8, 32, false}, {512, 10, 64, false}, {256, 8, 16, false}, {1024, 4, 16, false}, {512, 4, 16, true},
+    {1024, 4, 16, true},
 };
 constexpr int kNumSchedules = (int)(sizeof(kSchedules) / sizeof(kSchedules[0]));
 
@@ -64,6 +65,7 @@ static const void* scan_kernel_ptr(int schedule) {
     case 7: return (const void*)k_scan<PREC, NARROW, 256, 8, 16, false>;
     case 8: return (const void*)k_scan<PREC, NARROW, 1024, 4, 16, false>;
     case 9: return (const void*)k_scan<PREC, NARROW, 512, 4, 16, true>;
+    case 10: return (const void*)k_scan<PREC, NARROW, 1024, 4, 16, true>;
     default: return (const void*)k_scan<PREC, NARROW, 512, 8, 16, false>;
     }
 }

@@ -32,11 +32,12 @@ struct TabCap {
 // of more than 4 key units need up to 128 VGPRs per lane (the batch lives in
 // registers), so those launches stay at 4 waves per SIMD; the single-job
 // kernel with 4-unit batches fits in 64 VGPRs and may run 8 (the batched
-// kernel, which also holds the table refill, would spill there).
-template <int PREC, bool NARROW, int WG, int UNROLL, bool BATCHED>
+// kernel, which also holds the table refill, would spill there, and so would
+// the rotating loads, which also hold the fill stream).
+template <int PREC, bool NARROW, int WG, int UNROLL, bool BATCHED, bool RING = false>
 struct ScanOccupancy {
     static constexpr int wgs = TabCap<PREC, NARROW>::value * (int)sizeof(typename ScanTypes<PREC>::W) <= 65536 ? 2 : 1;
-    static constexpr int cap = UNROLL <= 4 && !BATCHED ? 8 : 4;
+    static constexpr int cap = UNROLL <= 4 && !BATCHED && !RING ? 8 : 4;
     static constexpr int waves_per_eu = wgs * WG / 256 < cap ? wgs * WG / 256 : cap;
 };
 

@@ -71,17 +71,17 @@ def test_batch_mixed_key_formats():
     bt.close()
 
 
-@pytest.mark.parametrize("precision", ["fp32_wide", "fp32_kahan"])
-def test_batch_rotating_loads(precision):
-    # schedule 9 (rotating loads) in the batched kernel, both key formats,
-    # against each job alone under the default schedule
+@pytest.mark.parametrize("precision,sched", [("fp32_wide", 9), ("fp32_kahan", 9), ("fp32_wide", 10)])
+def test_batch_rotating_loads(precision, sched):
+    # schedules 9 and 10 (rotating loads) in the batched kernel, both key
+    # formats, against each job alone under the default schedule
     specs = [((720, 0), 300, 600, 24, 7, 80.0), ((720, 1), 3, 4, 8, 2, 90.0),
              ((720, 2), 6000, 11000, 10, 3, 70.0), ((720, 3), 700, 500, 16, 5, 60.0)]
     data = _datasets(specs)
-    say(f"batch with rotating loads, {precision}")
+    say(f"batch with rotating loads, {precision}, schedule {sched}")
     bt = vb.BatchTrainer([(torch.from_numpy(i), torch.from_numpy(l)) for i, l in data], precision=precision,
-                         schedule_id=9)
-    assert [s for s, _ in bt.schedule()] == [9, 9]
+                         schedule_id=sched)
+    assert [s for s, _ in bt.schedule()] == [sched, sched]
     brecs = bt.train(4)
     for k, (images, labels) in enumerate(data):
         precs, pw = _plain(images, labels, 4, precision=precision)

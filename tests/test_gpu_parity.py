@@ -320,13 +320,14 @@ def test_schedules_agree():
         tr.close()
 
 
-# Schedule 9 scans with rotating loads: lanes scan a whole number of 4-unit
-# batches per feature (padding units add zero and hold no split) and the
-# loads run one batch ahead across feature boundaries.  Shapes: one key unit
-# per lane or less, exactly one batch, one unit past it, many batches with
-# remainder lanes, feature counts far below one workgroup step (empty groups
-# and waves), and 15-bit keys.
+# Schedules 9 and 10 scan with rotating loads (512 and 1024 threads): lanes
+# scan a whole number of 4-unit batches per feature (padding units add zero
+# and hold no split) and the loads run one batch ahead across feature
+# boundaries.  Shapes: one key unit per lane or less, exactly one batch, one
+# unit past it, many batches with remainder lanes, feature counts far below
+# one workgroup step (empty groups and waves), and 15-bit keys.
 ROTATING = 9
+ROTATING_SCHEDULES = (9, 10)
 
 
 @pytest.mark.parametrize("seed,n,size,levels", [
@@ -341,19 +342,20 @@ ROTATING = 9
 def test_rotating_loads_match_batched(seed, n, size, levels):
     images, labels = _tiny(seed, n, size, levels)
     say(f"rotating loads: seed={seed} n={n} size={size}")
-    assert vb.boost_schedule_count() > ROTATING
+    assert vb.boost_schedule_count() > max(ROTATING_SCHEDULES)
     precisions = ["fp32_wide", "fp32_kahan", "fp32"] + (["fp64"] if n <= 20000 else [])
     for precision in precisions:
         ref = _trainer(images, labels, precision=precision, schedule_id=0)
         a = ref.train(5)
         wa = ref.weights().cpu().numpy()
         ref.close()
-        tr = _trainer(images, labels, precision=precision, schedule_id=ROTATING)
-        b = tr.train(5)
-        wb = tr.weights().cpu().numpy()
-        tr.close()
-        assert b.tobytes() == a.tobytes(), precision
-        assert np.array_equal(wb, wa), precision
+        for sched in ROTATING_SCHEDULES:
+            tr = _trainer(images, labels, precision=precision, schedule_id=sched)
+            b = tr.train(5)
+            wb = tr.weights().cpu().numpy()
+            tr.close()
+            assert b.tobytes() == a.tobytes(), (precision, sched)
+            assert np.array_equal(wb, wa), (precision, sched)
 
 
 def test_rotating_loads_against_oracle(tiny):

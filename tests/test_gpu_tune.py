@@ -19,7 +19,7 @@ if not torch.cuda.is_available():
 from paper_1306_1467_amd import vjboost as vb  # noqa: E402
 
 # schedule table: (workgroup, units per batch, lanes per feature)
-LANES = [16, 16, 16, 16, 16, 32, 64, 16, 16, 16]
+LANES = [16, 16, 16, 16, 16, 32, 64, 16, 16, 16, 16]
 
 
 def say(msg):
