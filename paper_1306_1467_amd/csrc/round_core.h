@@ -51,7 +51,8 @@ __device__ __forceinline__ bool better(const WgBest& c, const WgBest& b) {
 // step and first unit of the next batch to load, pf / cf = that feature's
 // row and this lane's unit count there (0 past f1: the padding unit is read
 // instead).  prime() issues the first loads and may run before the LDS table
-// is filled; run() needs the table.
+// is filled; run() needs the table.  Slots past a feature's last owned unit
+// are loaded (from the padding unit) but not scanned.
 template <int PREC, bool NARROW, int UNROLL, int LPF>
 struct RingScan {
     static constexpr int G = 64 / LPF;
@@ -97,34 +98,44 @@ struct RingScan {
         }
     }
 
+    // One batch: scan the UNROLL slots in order (in a feature's last batch
+    // only its first `last` units, the ones some lane owns), reloading each
+    // slot from the fill stream as soon as it is scanned.
+    template <bool LAST>
+    __device__ __forceinline__ void step(LaneAcc<PREC>& a, const typename ScanTypes<PREC>::W* tab,
+                                         const JobDev& jd, int last) {
+        if (fill_full && rr + UNROLL <= per - 1) {
+            // every lane owns units rr .. rr + UNROLL - 1 (each owns at least per - 1)
+            const uint4* base = pf + rr * LPF;
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) {
+                if (!LAST || k < last) scan_unit<PREC, NARROW>(a, tab, u[k]);
+                u[k] = ld_stream(base + k * LPF);
+            }
+        } else if (fill_live) {
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) {
+                if (!LAST || k < last) scan_unit<PREC, NARROW>(a, tab, u[k]);
+                const int r = rr + k;
+                u[k] = ld_stream(r < cf ? pf + r * LPF : jd.pad);
+            }
+        } else {   // nothing left to load: the wave's last batch
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k)
+                if (!LAST || k < last) scan_unit<PREC, NARROW>(a, tab, u[k]);
+        }
+        advance_fill(jd);
+    }
+
     __device__ __forceinline__ WgBest run(const JobDev& jd, const typename ScanTypes<PREC>::W* tab, double tp,
                                           double tn, double2* __restrict__ ferr) {
         WgBest best{DBL_MAX, -1, 0, -1};
         if (!any) return best;
+        const int last = per - (nbr - 1) * UNROLL;   // units of a feature's last batch that some lane owns
         while (true) {
             LaneAcc<PREC> a;
-            for (int b = 0; b < nbr; ++b) {
-                if (fill_full && rr + UNROLL <= per - 1) {
-                    // every lane owns units rr .. rr + UNROLL - 1 (each owns at least per - 1)
-                    const uint4* base = pf + rr * LPF;
-#pragma unroll
-                    for (int k = 0; k < UNROLL; ++k) {
-                        scan_unit<PREC, NARROW>(a, tab, u[k]);
-                        u[k] = ld_stream(base + k * LPF);
-                    }
-                } else if (fill_live) {
-#pragma unroll
-                    for (int k = 0; k < UNROLL; ++k) {
-                        scan_unit<PREC, NARROW>(a, tab, u[k]);
-                        const int r = rr + k;
-                        u[k] = ld_stream(r < cf ? pf + r * LPF : jd.pad);
-                    }
-                } else {   // nothing left to load: the wave's last batch
-#pragma unroll
-                    for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
-                }
-                advance_fill(jd);
-            }
+            for (int b = 0; b + 1 < nbr; ++b) step<false>(a, tab, jd, 0);
+            step<true>(a, tab, jd, last);
             const FeatureScan fs = finish_feature<PREC, LPF>(a, threadIdx.x & 63, tp, tn);
             if (j < f1) {
                 if (ferr != nullptr && L == 0) ferr[j] = make_double2(fs.e_pos, fs.e_neg);
