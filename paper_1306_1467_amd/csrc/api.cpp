@@ -237,7 +237,7 @@ int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels
     // on failure, work already queued on the stream finishes before the call
     // returns: the caller may free the workspace right away
     auto fail = [&](int code) {
-        if (c->stream) hipStreamSynchronize(c->stream); else hipDeviceSynchronize();
+        if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
         delete c;
         return code;
     };
@@ -345,7 +345,7 @@ static int ensure_graph(boost_ctx* c) {
     if (rc == BOOST_OK) rc = update_launch(c->jd, c->plan.grid, c->stream);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(c->stream, &g);
-    if (rc != BOOST_OK) { if (g) hipGraphDestroy(g); return rc; }
+    if (rc != BOOST_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (e != hipSuccess) { set_error(std::string("graph capture: ") + hipGetErrorString(e)); return BOOST_E_DEVICE; }
     c->graph = g;
     VJB_HIP(hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
@@ -471,10 +471,10 @@ int boost_classify_train(boost_ctx* c, const boost_stump* stumps, int32_t T, uin
 
 void boost_destroy(boost_ctx* c) {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream); else hipDeviceSynchronize();
-    if (c->gexec) hipGraphExecDestroy(c->gexec);
-    if (c->graph) hipGraphDestroy(c->graph);
-    for (hipEvent_t e : c->ev) hipEventDestroy(e);
+    if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     delete c;
 }
 

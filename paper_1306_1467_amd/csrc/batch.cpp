@@ -231,7 +231,7 @@ int boost_batch_init(boost_batch** out, int32_t n_jobs, const boost_job* jobs, c
     // on failure, work already queued on the stream finishes before the call
     // returns: the caller may free the workspace right away
     auto fail = [&](int code) {
-        if (b->stream) hipStreamSynchronize(b->stream); else hipDeviceSynchronize();
+        if (b->stream) (void)hipStreamSynchronize(b->stream); else (void)hipDeviceSynchronize();
         delete b;
         return code;
     };
@@ -316,7 +316,7 @@ static int batch_graph(boost_batch* b) {
     if (rc == BOOST_OK) rc = batch_update_launch(b->opts.precision, (int)b->n_upd, b->bd, b->stream);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->stream, &g);
-    if (rc != BOOST_OK) { if (g) hipGraphDestroy(g); return rc; }
+    if (rc != BOOST_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (e != hipSuccess) { set_error(std::string("graph capture: ") + hipGetErrorString(e)); return BOOST_E_DEVICE; }
     b->graph = g;
     VJB_HIP(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
@@ -402,10 +402,10 @@ int boost_batch_get_timing(boost_batch* b, double out[4]) {
 
 void boost_batch_destroy(boost_batch* b) {
     if (!b) return;
-    if (b->stream) hipStreamSynchronize(b->stream); else hipDeviceSynchronize();
-    if (b->gexec) hipGraphExecDestroy(b->gexec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    for (hipEvent_t e : b->ev) hipEventDestroy(e);
+    if (b->stream) (void)hipStreamSynchronize(b->stream); else (void)hipDeviceSynchronize();
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     delete b;
 }
 

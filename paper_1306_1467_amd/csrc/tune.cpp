@@ -18,7 +18,7 @@ int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, d
     hipEvent_t e[2];
     VJB_HIP(hipEventCreate(&e[0]));
     if (hipEventCreate(&e[1]) != hipSuccess) {
-        hipEventDestroy(e[0]);
+        (void)hipEventDestroy(e[0]);
         set_error("hipEventCreate failed");
         return BOOST_E_DEVICE;
     }
@@ -36,8 +36,8 @@ int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, d
         if (ms < best_ms) best_ms = ms;
     }
     if (rc == BOOST_E_DEVICE) set_error("timing a candidate schedule failed");
-    hipEventDestroy(e[0]);
-    hipEventDestroy(e[1]);
+    (void)hipEventDestroy(e[0]);
+    (void)hipEventDestroy(e[1]);
     return rc;
 }
 
