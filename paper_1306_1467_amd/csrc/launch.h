@@ -47,6 +47,7 @@ int probe_launch(const ScanPlan& p, int schedule, const JobDev& jd, uint32_t* si
 // tune.cpp: measured schedule choice
 constexpr int kTuneReps = 5;        // timed launches per candidate of a single job (the minimum counts)
 constexpr int kTuneRepsBatch = 3;   // the same for a batch (its launches are longer)
+constexpr double kTunePrune = 1.03;  // a single job's candidates this much slower than the best stop after two rounds
 // Runs launch() once untimed (when warm), then `reps` times each bracketed by
 // HIP events on s; best_ms is the fastest.
 int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, double& best_ms, bool warm = true);

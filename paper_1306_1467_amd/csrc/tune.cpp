@@ -80,19 +80,31 @@ int tune_single(const JobDev& jd, int precision, int num_cu, int device, hipStre
         plans.push_back(p);
     }
     if (ids.empty()) { set_error("no launch schedule fits this job"); return BOOST_E_INVALID; }
-    // candidates are timed in turn, kTuneReps rounds over all of them, so that
-    // slow drifts of the clock do not favour one; each keeps its fastest
-    // launch.  Round 0 only warms every candidate up (one untimed launch).
+    // candidates are timed in turn, kTuneReps rounds over all of them, in
+    // alternating order, so that slow drifts of the clock (it is still rising
+    // in the first rounds) do not favour one; each keeps its fastest launch.
+    // Round 0 only warms every candidate up (one untimed launch).  After two
+    // timed rounds, candidates more than kTunePrune slower than the fastest
+    // are not timed again (run-to-run noise is about 1 %).
     std::vector<double> best(ids.size(), 1e300);
+    std::vector<char> alive(ids.size(), 1);
     int rc;
-    for (int rep = 0; rep <= kTuneReps; ++rep)
-        for (size_t c = 0; c < ids.size(); ++c) {
+    for (int rep = 0; rep <= kTuneReps; ++rep) {
+        for (size_t i = 0; i < ids.size(); ++i) {
+            const size_t c = rep % 2 ? i : ids.size() - 1 - i;
+            if (!alive[c]) continue;
             double ms = 0;
             if ((rc = time_launches(s, rep == 0 ? 0 : 1, [&]() { return scan_launch(plans[c], jd, nullptr, s); }, ms,
                                     rep == 0)) != BOOST_OK)
                 return rc;
             if (rep > 0 && ms < best[c]) best[c] = ms;
         }
+        if (rep == 2) {
+            double bmin = 1e300;
+            for (size_t c = 0; c < ids.size(); ++c) bmin = best[c] < bmin ? best[c] : bmin;
+            for (size_t c = 0; c < ids.size(); ++c) alive[c] = best[c] <= bmin * kTunePrune;
+        }
+    }
     size_t win = 0;
     for (size_t c = 0; c < ids.size(); ++c) {
         ms_out[ids[c]] = best[c];
