@@ -306,6 +306,9 @@ def main():
                     help="schedule of the batched and the plain per-job runs (-1: measured choice at init)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run one device copy of this many GiB first (counter calibration)")
+    ap.add_argument("--prep-only", action="store_true",
+                    help="only the one-time preparation of the headline workload (fixed schedule 0, no tuning), "
+                         "then exit: the run a profile of the preparation kernels needs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: vjboost runs on one GPU only; multi-GPU runs are not supported "
@@ -324,6 +327,15 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.prep_only:
+        images, labels = synth.workload_jobs("faces15k")[0].make()
+        t0 = time.perf_counter()
+        tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=args.precision, schedule_id=0)
+        torch.cuda.synchronize()
+        print(json.dumps({"prep_only": True, "init_ms": round((time.perf_counter() - t0) * 1e3, 1),
+                          "features": tr.F, "windows": tr.n}), flush=True)
+        tr.close()
+        return
     res, images, labels = run_single(args, torch, vb, synth)
     line = {
         "metric": METRIC,

@@ -266,6 +266,43 @@ int boost_get_sorted(boost_ctx *c, int64_t j0, int64_t nf, int32_t *d_order, uin
 int boost_classify_train(boost_ctx *c, const boost_stump *stumps, int32_t T,
                          uint8_t *d_out, double *d_score);
 
+/* Training-error curve of the Section 2.3 strong classifier: d_err_curve
+ * (device int32[T]) receives, for t = 1..T, the number of the context's
+ * training windows that the classifier built from the first t stumps
+ * (C_t(x) = 1 iff sum_{u<=t} alpha_u h_u(x) >= 1/2 sum_{u<=t} alpha_u)
+ * misclassifies, in one launch.  stumps as for boost_classify_train.
+ * Synchronises.  BOOST_E_INVALID for NULL pointers, T outside 0..4096 or an
+ * invalid record. */
+int boost_classify_train_curve(boost_ctx *c, const boost_stump *stumps, int32_t T, int32_t *d_err_curve);
+
+/* The Section 2.3 strong classifier on any windows (held-out or new ones),
+ * with no training context: C(x) = 1 iff sum_t alpha_t h_t(x) >= 1/2 sum_t
+ * alpha_t, h_t(x) = 1 iff p_t f_t(x) < p_t theta_t (Section 2.2), where f_t
+ * is the Haar feature the record describes (type, x, y, cell_w, cell_h).
+ *   d_images     n x window_h x window_w uint8, row-major per window (device).
+ *   d_labels     NULL or device uint8[n] (1 = positive); needed for the curve.
+ *   stumps       host array of T records (0 <= T <= 4096; type, x, y, cell_w,
+ *                cell_h, polarity, threshold and alpha are read).
+ *   d_out        NULL or device uint8[n]: decisions of the classifier of all T stumps.
+ *   d_score      NULL or device double[n]: sum_t alpha_t h_t(x).
+ *   d_err_curve  NULL or device int32[T]: for t = 1..T, the windows whose
+ *                label differs from the decision of the first t stumps
+ *                (a label other than 0 / 1 counts as an error).
+ *   stream       hipStream_t (NULL: the legacy default stream).
+ *   d_workspace  caller-owned device memory of at least
+ *                boost_classify_workspace_bytes(n, window_w, window_h) bytes
+ *                (the windows' integral images and the stump table).
+ * Sums run in stump order in FP64, so each decision equals the definition
+ * evaluated in that order.  Synchronises.  BOOST_E_INVALID for NULL images,
+ * n < 1, a window outside 1..32, T outside 0..4096, a curve without labels,
+ * or a record whose polarity is not +-1, whose alpha is not finite or whose
+ * feature does not fit the window; BOOST_E_NOMEM for a short workspace. */
+size_t boost_classify_workspace_bytes(int64_t n, int32_t window_w, int32_t window_h);
+int boost_classify(const uint8_t *d_images, int64_t n, int32_t window_w, int32_t window_h,
+                   const uint8_t *d_labels, const boost_stump *stumps, int32_t T,
+                   uint8_t *d_out, double *d_score, int32_t *d_err_curve,
+                   void *stream, void *d_workspace, size_t workspace_bytes);
+
 void boost_destroy(boost_ctx *c);
 
 /* ------------------------------------------------------------ batched jobs

@@ -14,7 +14,6 @@ static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 const char* get_error() { return g_err.c_str(); }
 
-constexpr int kMaxClassifyT = 4096;
 constexpr int64_t kMaxFp64N = 20000;   // FP64 weight table must fit in LDS
 
 bool valid_options(const boost_options* o) {
@@ -133,6 +132,7 @@ int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, cons
         set_error("both classes need at least one window (1/(2l) and 1/(2m) must exist)");
         return BOOST_E_INVALID;
     }
+    h.n_pos = st.n_pos;
     if ((rc = integral_launch(jd, d_images, s)) != BOOST_OK) return rc;
     if ((rc = sort_launch(jd, h.scratch, num_cu, s)) != BOOST_OK) return rc;
     if ((rc = init_weights_launch(jd, s)) != BOOST_OK) return rc;
@@ -152,7 +152,7 @@ struct boost_ctx {
     hipStream_t stream = nullptr;
     boost_options opts;
     boost_feature_set fs;
-    int64_t n = 0, F = 0;
+    int64_t n = 0, F = 0, n_pos = 0;
     ScanPlan plan;
     int schedule = 0;
     std::vector<double> tune_ms;
@@ -250,6 +250,7 @@ int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels
     if ((rc = setup_job(h, (char*)d_workspace, n, fs, o, d_images, d_labels, c->num_cu, c->stream)) != BOOST_OK)
         return fail(rc);
     c->jd = h.jd;
+    c->n_pos = h.n_pos;
     c->wtmp = h.wtmp;
     c->cls = h.cls;
     c->scratch = h.scratch;
@@ -444,8 +445,9 @@ int boost_get_sorted(boost_ctx* c, int64_t j0, int64_t nf, int32_t* d_order, uin
     return sorted_out_launch(c->jd, j0, nf, d_order, d_run_end, c->stream);
 }
 
-int boost_classify_train(boost_ctx* c, const boost_stump* stumps, int32_t T, uint8_t* d_out, double* d_score) {
-    if (!c || !d_out || T < 0 || (T > 0 && !stumps)) { set_error("invalid arguments"); return BOOST_E_INVALID; }
+static int classify_train(boost_ctx* c, const boost_stump* stumps, int32_t T, uint8_t* d_out, double* d_score,
+                          int32_t* d_err_curve) {
+    if (T < 0 || (T > 0 && !stumps)) { set_error("invalid arguments"); return BOOST_E_INVALID; }
     if (T > kMaxClassifyT) { set_error("at most 4096 stumps"); return BOOST_E_INVALID; }
     std::vector<StumpDev> h((size_t)(T > 0 ? T : 1));
     for (int t = 0; t < T; ++t) {
@@ -463,10 +465,21 @@ int boost_classify_train(boost_ctx* c, const boost_stump* stumps, int32_t T, uin
         h[t].alpha = s.alpha;
     }
     if (T > 0) VJB_HIP(hipMemcpyAsync(c->cls, h.data(), (size_t)T * sizeof(StumpDev), hipMemcpyHostToDevice, c->stream));
-    int rc = classify_launch(c->jd, c->cls, T, d_out, d_score, c->stream);
+    int rc = classify_any_launch(c->jd.ii, c->jd.ii_stride, c->jd.W, c->n, c->cls, T, c->jd.perm, nullptr,
+                                 d_err_curve ? (int64_t)c->n_pos : -1, d_out, d_score, d_err_curve, c->stream);
     if (rc != BOOST_OK) return rc;
     VJB_HIP(hipStreamSynchronize(c->stream));   // the host array h is read by the copy
     return BOOST_OK;
+}
+
+int boost_classify_train(boost_ctx* c, const boost_stump* stumps, int32_t T, uint8_t* d_out, double* d_score) {
+    if (!c || !d_out) { set_error("invalid arguments"); return BOOST_E_INVALID; }
+    return classify_train(c, stumps, T, d_out, d_score, nullptr);
+}
+
+int boost_classify_train_curve(boost_ctx* c, const boost_stump* stumps, int32_t T, int32_t* d_err_curve) {
+    if (!c || !d_err_curve) { set_error("invalid arguments"); return BOOST_E_INVALID; }
+    return classify_train(c, stumps, T, nullptr, nullptr, d_err_curve);
 }
 
 void boost_destroy(boost_ctx* c) {

@@ -166,15 +166,18 @@ static int time_part(boost_batch* b, int p, double& ms) {
 // Measured choice for one key format: first the schedule (with the default
 // segment granularity), then the segments per workgroup.
 static int tune_part(boost_batch* b, int p) {
-    std::string key = "batch/" + std::to_string(b->device) + "/" + std::to_string(b->opts.precision) + "/" +
+    std::string key = "batch/" + tune_device_tag(b->device) + "/" + std::to_string(b->opts.precision) + "/" +
                       std::to_string(p);
     for (const JobHost& h : b->jobs)
         if ((h.jd.g.narrow ? 0 : 1) == p) key += "/" + std::to_string(h.jd.g.n) + "x" + std::to_string(h.jd.F);
     std::vector<int> hit;
     int rc;
-    if (tune_cache_get(key, hit)) {
-        if ((rc = part_config(b->part[p], b->opts.precision, p == 0, hit[0], b->num_cu)) != BOOST_OK) return rc;
-        b->part[p].spw = hit[1];
+    PartCfg cached;
+    if (tune_cache_get(key, hit) && hit.size() == 2 && hit[0] >= 0 && hit[0] < scan_schedule_count() &&
+        scan_schedule_lanes(hit[0]) == scan_schedule_lanes(b->part[p].schedule) && hit[1] >= 1 &&
+        hit[1] <= kMaxSegsPerWg && part_config(cached, b->opts.precision, p == 0, hit[0], b->num_cu) == BOOST_OK) {
+        cached.spw = hit[1];   // entries that do not fit are ignored and re-tuned
+        b->part[p] = cached;
         return upload_segments(b);
     }
     const int lanes = scan_schedule_lanes(b->part[p].schedule);

@@ -1,0 +1,190 @@
+// The strong classifier of Section 2.3 on any set of windows:
+//     C(x) = 1  iff  sum_t alpha_t h_t(x) >= 1/2 sum_t alpha_t,
+// with h_t(x) = 1 iff p_t f_t(x) < p_t theta_t (Section 2.2), and, when labels
+// are known, the training / test error of every prefix classifier C_1 .. C_T
+// (the first t stumps) in the same launch.
+//
+// One thread per window walks the stumps in order, keeping s_t (the alpha of
+// the stumps that vote 1) and A_t (all alphas so far) in FP64 and in that
+// order; C_t(x) = [s_t >= A_t / 2].  The stump table is uniform across the
+// workgroup (scalar loads); the feature values come from sample-minor
+// integral images, so a wave's corner reads are coalesced.  Wrong decisions
+// are counted per prefix with one wave ballot per stump, per workgroup in LDS,
+// then added to the output curve with one atomic per (workgroup, stump).
+#include <math.h>
+
+#include <string>
+#include <vector>
+
+#include "launch.h"
+
+namespace vjb {
+
+constexpr int kClsWg = 256;
+
+// LABELS: 0 none, 1 caller's labels (array in caller order), 2 internal
+// positives-first order (y = [i < l]).
+template <int LABELS>
+__global__ __launch_bounds__(kClsWg) void k_classify_any(const int32_t* __restrict__ ii, int64_t S, int wp1, int64_t n,
+                                                         const StumpDev* __restrict__ st, int T,
+                                                         const int32_t* __restrict__ perm,
+                                                         const uint8_t* __restrict__ labels, int64_t l,
+                                                         uint8_t* __restrict__ out, double* __restrict__ score,
+                                                         int32_t* __restrict__ curve) {
+    __shared__ int32_t cnt[kMaxClassifyT];
+    const int64_t i = (int64_t)blockIdx.x * kClsWg + threadIdx.x;
+    const bool live = i < n;
+    const int64_t e = live ? (perm != nullptr ? (int64_t)perm[i] : i) : 0;
+    int y = 0;
+    if constexpr (LABELS == 1) y = live ? (int)labels[e] : 0;
+    if constexpr (LABELS == 2) y = i < l ? 1 : 0;
+    if constexpr (LABELS != 0) {
+        for (int t = threadIdx.x; t < T; t += kClsWg) cnt[t] = 0;
+        __syncthreads();
+    }
+    double s = 0.0, a = 0.0;
+    for (int t = 0; t < T; ++t) {
+        const StumpDev sd = st[t];
+        const int32_t f = live ? haar_value(ii, S, wp1, sd.desc, i) : 0;
+        if ((int64_t)sd.polarity * f < (int64_t)sd.polarity * sd.theta) s += sd.alpha;
+        a += sd.alpha;
+        if constexpr (LABELS != 0) {
+            const int c = s >= 0.5 * a ? 1 : 0;
+            const unsigned long long wrong = __ballot(live && c != y);
+            if ((threadIdx.x & 63) == 0 && wrong != 0ull) atomicAdd(&cnt[t], (int32_t)__popcll(wrong));
+        }
+    }
+    if (live) {
+        if (out != nullptr) out[e] = s >= 0.5 * a ? 1 : 0;
+        if (score != nullptr) score[e] = s;
+    }
+    if constexpr (LABELS != 0) {
+        __syncthreads();
+        if (curve != nullptr)
+            for (int t = threadIdx.x; t < T; t += kClsWg)
+                if (cnt[t] != 0) atomicAdd(&curve[t], cnt[t]);
+    }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t m, int32_t v) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) p[k] = v;
+}
+
+int classify_any_launch(const int32_t* ii, int64_t S, int W, int64_t n, const StumpDev* d_stumps, int T,
+                        const int32_t* perm, const uint8_t* labels, int64_t l, uint8_t* d_out, double* d_score,
+                        int32_t* d_curve, hipStream_t s) {
+    if (d_curve != nullptr && T > 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, d_curve, (int64_t)T, 0);
+        VJB_HIP(hipGetLastError());
+    }
+    const dim3 grid((unsigned)((n + kClsWg - 1) / kClsWg)), block(kClsWg);
+    if (labels != nullptr)
+        hipLaunchKernelGGL(k_classify_any<1>, grid, block, 0, s, ii, S, W + 1, n, d_stumps, T, perm, labels, l, d_out,
+                           d_score, d_curve);
+    else if (l >= 0)
+        hipLaunchKernelGGL(k_classify_any<2>, grid, block, 0, s, ii, S, W + 1, n, d_stumps, T, perm, labels, l, d_out,
+                           d_score, d_curve);
+    else
+        hipLaunchKernelGGL(k_classify_any<0>, grid, block, 0, s, ii, S, W + 1, n, d_stumps, T, perm, labels, l, d_out,
+                           d_score, d_curve);
+    VJB_HIP(hipGetLastError());
+    return BOOST_OK;
+}
+
+// Checks stump records against a window and packs them for the device:
+// polarity +-1, finite alpha, a known type whose cells fit the window.
+int pack_stumps(const boost_stump* stumps, int T, int W, int H, StumpDev* out) {
+    static const int kBw[5] = {3, 1, 2, 1, 2};
+    static const int kBh[5] = {1, 3, 1, 2, 2};
+    for (int t = 0; t < T; ++t) {
+        const boost_stump& r = stumps[t];
+        const bool ok = r.type >= 0 && r.type < 5 && r.cell_w >= 1 && r.cell_h >= 1 && r.x >= 0 && r.y >= 0 &&
+                        r.x + kBw[r.type < 0 || r.type > 4 ? 0 : r.type] * r.cell_w <= W &&
+                        r.y + kBh[r.type < 0 || r.type > 4 ? 0 : r.type] * r.cell_h <= H &&
+                        (r.polarity == 1 || r.polarity == -1) && isfinite(r.alpha);
+        if (!ok) {
+            set_error("invalid stump record " + std::to_string(t) + " for a " + std::to_string(W) + "x" +
+                      std::to_string(H) + " window");
+            return BOOST_E_INVALID;
+        }
+        out[t].desc = pack_feature(r.type, r.x, r.y, r.cell_w, r.cell_h);
+        out[t].polarity = r.polarity;
+        out[t].theta = r.threshold;
+        out[t].pad = 0;
+        out[t].alpha = r.alpha;
+    }
+    return BOOST_OK;
+}
+
+// Layout of the caller's workspace: integral images, then the stump table.
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+static size_t classify_ii_bytes(int64_t n, int W, int H) {
+    return a256((size_t)(W + 1) * (size_t)(H + 1) * (size_t)ii_stride_of(n) * 4);
+}
+static size_t classify_bytes(int64_t n, int W, int H) {
+    return classify_ii_bytes(n, W, H) + a256((size_t)kMaxClassifyT * sizeof(StumpDev));
+}
+
+static int check_classify_args(const uint8_t* d_images, int64_t n, int32_t W, int32_t H, const boost_stump* stumps,
+                               int32_t T, const uint8_t* d_labels, int32_t* d_err_curve) {
+    if (!d_images || n < 1 || W < 1 || W > kMaxWindow || H < 1 || H > kMaxWindow) {
+        set_error("classify: NULL images, n < 1 or a window outside 1..32");
+        return BOOST_E_INVALID;
+    }
+    if (T < 0 || T > kMaxClassifyT || (T > 0 && !stumps)) {
+        set_error("classify: 0..4096 stumps required");
+        return BOOST_E_INVALID;
+    }
+    if (d_err_curve && !d_labels) {
+        set_error("classify: the error curve needs labels");
+        return BOOST_E_INVALID;
+    }
+    return BOOST_OK;
+}
+
+// Integral images of the windows, the stump table, then the classifier, on
+// stream s, with ii / tab in device memory the caller or the library owns.
+static int classify_windows(const uint8_t* d_images, int64_t n, int32_t W, int32_t H, const uint8_t* d_labels,
+                            const boost_stump* stumps, int32_t T, uint8_t* d_out, double* d_score,
+                            int32_t* d_err_curve, hipStream_t s, int32_t* ii, StumpDev* tab) {
+    std::vector<StumpDev> h((size_t)(T > 0 ? T : 1));
+    int rc = pack_stumps(stumps, T, W, H, h.data());
+    if (rc != BOOST_OK) return rc;
+    const int64_t S = ii_stride_of(n);
+    if ((rc = integral_raw_launch(d_images, nullptr, n, W, H, ii, S, s)) != BOOST_OK) return rc;
+    if (T > 0) VJB_HIP(hipMemcpyAsync(tab, h.data(), (size_t)T * sizeof(StumpDev), hipMemcpyHostToDevice, s));
+    rc = classify_any_launch(ii, S, W, n, tab, T, nullptr, d_labels, -1, d_out, d_score, d_err_curve, s);
+    if (rc != BOOST_OK) return rc;
+    VJB_HIP(hipStreamSynchronize(s));   // the host table h is read by the copy
+    return BOOST_OK;
+}
+
+}  // namespace vjb
+
+using namespace vjb;
+
+extern "C" {
+
+size_t boost_classify_workspace_bytes(int64_t n, int32_t window_w, int32_t window_h) {
+    if (n < 1 || window_w < 1 || window_w > kMaxWindow || window_h < 1 || window_h > kMaxWindow) return 0;
+    return classify_bytes(n, window_w, window_h);
+}
+
+int boost_classify(const uint8_t* d_images, int64_t n, int32_t window_w, int32_t window_h, const uint8_t* d_labels,
+                   const boost_stump* stumps, int32_t T, uint8_t* d_out, double* d_score, int32_t* d_err_curve,
+                   void* stream, void* d_workspace, size_t workspace_bytes) {
+    int rc = check_classify_args(d_images, n, window_w, window_h, stumps, T, d_labels, d_err_curve);
+    if (rc != BOOST_OK) return rc;
+    if (!d_workspace) { set_error("classify: NULL workspace"); return BOOST_E_INVALID; }
+    const size_t need = classify_bytes(n, window_w, window_h);
+    if (workspace_bytes < need) {
+        set_error("classify: workspace too small: need " + std::to_string(need) + " bytes");
+        return BOOST_E_NOMEM;
+    }
+    char* ws = (char*)d_workspace;
+    return classify_windows(d_images, n, window_w, window_h, d_labels, stumps, T, d_out, d_score, d_err_curve,
+                            (hipStream_t)stream, (int32_t*)ws, (StumpDev*)(ws + classify_ii_bytes(n, window_w, window_h)));
+}
+
+}  // extern "C"

@@ -1,7 +1,6 @@
 // One-time and inspection kernels of one job: ingest (positives-first order),
 // integral images (Section 2.1), initial weights (Section 2.3 Table 2), weight
-// get/set, feature values (Section 2.2), decoding of the sorted keys, and the
-// strong classifier of Section 2.3.
+// get/set, feature values (Section 2.2) and decoding of the sorted keys.
 #include "launch.h"
 #include "scan_core.h"
 
@@ -81,13 +80,14 @@ int ingest_launch(const JobDev& jd, const uint8_t* d_labels, int64_t n, hipStrea
 }
 
 // ---------------------------------------------------------------- integral images
-// One thread per window (internal order); ii[(r*(W+1)+c)*S + i], so a wave's
-// 64 windows write 256 contiguous bytes per position.
+// One thread per window; ii[(r*(W+1)+c)*S + i], so a wave's 64 windows write
+// 256 contiguous bytes per position.  Sample i is window perm[i] of the
+// images (or window i when perm is NULL).
 __global__ void k_integral(const uint8_t* __restrict__ images, const int32_t* __restrict__ perm, int64_t n, int W,
                            int H, int32_t* __restrict__ ii, int64_t S) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint8_t* img = images + (int64_t)perm[i] * W * H;
+    const uint8_t* img = images + (perm != nullptr ? (int64_t)perm[i] : i) * W * H;
     const int wp1 = W + 1;
     for (int c = 0; c <= W; ++c) ii[(int64_t)c * S + i] = 0;
     for (int r = 0; r < H; ++r) {
@@ -101,12 +101,15 @@ __global__ void k_integral(const uint8_t* __restrict__ images, const int32_t* __
     }
 }
 
-int integral_launch(const JobDev& jd, const uint8_t* d_images, hipStream_t s) {
-    const int64_t n = jd.g.n;
-    hipLaunchKernelGGL(k_integral, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_images, jd.perm, n, jd.W,
-                       jd.H, (int32_t*)jd.ii, jd.ii_stride);
+int integral_raw_launch(const uint8_t* d_images, const int32_t* perm, int64_t n, int W, int H, int32_t* ii, int64_t S,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_integral, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_images, perm, n, W, H, ii, S);
     VJB_HIP(hipGetLastError());
     return BOOST_OK;
+}
+
+int integral_launch(const JobDev& jd, const uint8_t* d_images, hipStream_t s) {
+    return integral_raw_launch(d_images, jd.perm, jd.g.n, jd.W, jd.H, (int32_t*)jd.ii, jd.ii_stride, s);
 }
 
 // ---------------------------------------------------------------- weights
@@ -236,33 +239,6 @@ int sorted_out_launch(const JobDev& jd, int64_t j0, int64_t nf, int32_t* d_order
                            d_order + c * n, d_flags + c * n);
         VJB_HIP(hipGetLastError());
     }
-    return BOOST_OK;
-}
-
-// ---------------------------------------------------------------- strong classifier
-// C(x) = 1 iff sum_t alpha_t h_t(x) >= 1/2 sum_t alpha_t (Section 2.3).
-__global__ void k_classify(JobDev jd, const StumpDev* __restrict__ st, int T, uint8_t* __restrict__ out,
-                           double* __restrict__ score) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= jd.g.n) return;
-    double half = 0.0;
-    for (int t = 0; t < T; ++t) half += st[t].alpha;
-    half *= 0.5;
-    double s = 0.0;
-    for (int t = 0; t < T; ++t) {
-        const int32_t f = haar_value(jd.ii, jd.ii_stride, jd.W + 1, st[t].desc, i);
-        const int64_t p = st[t].polarity;
-        if (p * f < p * st[t].theta) s += st[t].alpha;
-    }
-    const int64_t e = jd.perm[i];
-    out[e] = s >= half ? 1 : 0;
-    if (score) score[e] = s;
-}
-
-int classify_launch(const JobDev& jd, const StumpDev* d_stumps, int T, uint8_t* d_out, double* d_score, hipStream_t s) {
-    const int64_t n = jd.g.n;
-    hipLaunchKernelGGL(k_classify, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, jd, d_stumps, T, d_out, d_score);
-    VJB_HIP(hipGetLastError());
     return BOOST_OK;
 }
 

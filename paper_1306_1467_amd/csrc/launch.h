@@ -10,6 +10,7 @@
 namespace vjb {
 
 constexpr int kMaxScanGrid = 8192;   // upper bound of scan workgroups (per-workgroup records)
+constexpr int kMaxClassifyT = 4096;  // stumps per classifier call
 constexpr int kMaxSortGrid = 1024;   // upper bound of sort workgroups (fallback scratch)
 constexpr int kMaxPart = (int)((kMaxN + kUpdWg - 1) / kUpdWg);   // update workgroups of the largest job (<= 128)
 static_assert(kMaxPart <= 128, "weight_sum reads at most 128 partials");
@@ -24,7 +25,7 @@ struct ScanPlan {
 };
 
 // api.cpp: one job's layout and one-time preparation (shared by the batch)
-struct JobHost { JobDev jd; double* wtmp; StumpDev* cls; uint64_t* scratch; };
+struct JobHost { JobDev jd; double* wtmp; StumpDev* cls; uint64_t* scratch; int64_t n_pos; };
 int check_job_args(int64_t n, const boost_feature_set* fs, const boost_options* o);
 size_t job_bytes(int64_t n, const boost_feature_set* fs);
 int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, const boost_options* o,
@@ -51,6 +52,7 @@ constexpr double kTunePrune = 1.03;  // a single job's candidates this much slow
 // Runs launch() once untimed (when warm), then `reps` times each bracketed by
 // HIP events on s; best_ms is the fastest.
 int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, double& best_ms, bool warm = true);
+std::string tune_device_tag(int device);   // architecture, compute units, schedule table revision
 bool tune_cache_get(const std::string& key, std::vector<int>& choice);
 void tune_cache_put(const std::string& key, const std::vector<int>& choice);
 // Times every schedule with the job's lane count; ms_out[k] = -1 for schedules
@@ -66,7 +68,19 @@ int get_weights_launch(const JobDev& jd, double* d_out, hipStream_t s);
 int feature_values_launch(const JobDev& jd, int64_t j0, int64_t nf, int32_t* d_out, hipStream_t s);
 int integral_out_launch(const JobDev& jd, int32_t* d_out, hipStream_t s);
 int sorted_out_launch(const JobDev& jd, int64_t j0, int64_t nf, int32_t* d_order, uint8_t* d_flags, hipStream_t s);
-int classify_launch(const JobDev& jd, const StumpDev* d_stumps, int T, uint8_t* d_out, double* d_score, hipStream_t s);
+// integral images of n windows (images n x H x W row-major; window perm[i] at
+// sample i, or window i when perm is NULL) into ii[(H+1)(W+1)][S]
+int integral_raw_launch(const uint8_t* d_images, const int32_t* perm, int64_t n, int W, int H, int32_t* ii, int64_t S,
+                        hipStream_t s);
+
+// k_classify.hip: the strong classifier over n windows of sample-minor
+// integral images; labels (caller order) or, when NULL and l >= 0, y = [i < l];
+// perm maps sample i to the caller's index (NULL: identity).  d_curve[t] =
+// windows misclassified by the first t + 1 stumps (needs labels or l >= 0).
+int classify_any_launch(const int32_t* ii, int64_t S, int W, int64_t n, const StumpDev* d_stumps, int T,
+                        const int32_t* perm, const uint8_t* labels, int64_t l, uint8_t* d_out, double* d_score,
+                        int32_t* d_curve, hipStream_t s);
+int pack_stumps(const boost_stump* stumps, int T, int W, int H, StumpDev* out);
 
 // k_sort.hip
 int64_t sort_pow2(int64_t n);

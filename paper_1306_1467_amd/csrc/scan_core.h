@@ -24,15 +24,18 @@
 namespace vjb {
 
 // Masked candidates: at a position that is not the end of a run of equal
-// values the candidate becomes a quiet NaN, which v_max / v_min ignore (IEEE
-// maxNum / minNum: a quiet NaN operand yields the other operand).  The mask
-// is added rather than merged: a candidate is v + z with z = +0 (a split
+// values the candidate becomes a quiet NaN, which v_max / v_min ignore.  The
+// mask is added rather than merged: a candidate is v + z with z = +0 (a split
 // here: v + 0 = v exactly, -0 aside, which compares equal to +0) or z = the
-// all-ones pattern, a quiet NaN (no split: the sum is a quiet NaN).  The
-// addition writes a fresh register (pair), so the running sum needs no copy.
-// The scan translation unit is built with -fno-honor-nans so that no
-// canonicalisation is inserted around the max / min; the only NaN values are
-// these masks and the sums they poison.
+// all-ones pattern, a quiet NaN (no split: the IEEE sum of a number and a
+// quiet NaN is a quiet NaN).  The addition writes a fresh register (pair), so
+// the running sum needs no copy.  Both steps are defined behaviour: NaNs are
+// honoured in every translation unit (no -ffast-math, no -fno-honor-nans), an
+// IEEE addition with a quiet NaN operand returns a quiet NaN, and fmax / fmin
+// (LLVM maxnum / minnum, IEEE-754 maxNum / minNum) return the other operand
+// when one operand is a quiet NaN.  The sum is an arithmetic result, which
+// the compiler knows is not a signalling NaN, so no canonicalisation is
+// inserted in front of the max / min.
 __device__ __forceinline__ double nan_or_zero(uint32_t m) {
     return __longlong_as_double((long long)((uint64_t)m << 32));
 }
@@ -50,56 +53,79 @@ template <> struct ScanTypes<BOOST_PREC_FP64>       { using W = double; using A 
 template <> struct ScanTypes<BOOST_PREC_FP32_WIDE>  { using W = float;  using A = double; };
 
 // Per-lane accumulator.  A = type used across lanes and for the final errors.
-// cand(v, m): v is a candidate unless m is all ones (no split at this rank).
+// key(w, m): add the next key's table value w to the running sum; the sum is
+// a candidate unless m is all ones (no split after this rank).  total(),
+// vmax(), vmin(): the lane's local sum and extremes (vmax = -4 / vmin = +4
+// when the lane holds no split point: every real prefix lies in [-1, 1]).
 template <int PREC> struct LaneAcc;
 
 template <> struct LaneAcc<BOOST_PREC_FP32> {
     float s = 0.f, mx = -4.f, mn = 4.f;
-    __device__ __forceinline__ float add(float w) { s += w; return s; }
-    __device__ __forceinline__ void cand(float v, uint32_t m) {
-        const float c = v + nan_or_zero32(m);
+    __device__ __forceinline__ void key(float w, uint32_t m) {
+        s += w;
+        const float c = s + nan_or_zero32(m);
         mx = fmaxf(mx, c);
         mn = fminf(mn, c);
     }
+    __device__ __forceinline__ void unit_end() {}
     __device__ __forceinline__ float total() const { return s; }
     __device__ __forceinline__ float vmax() const { return mx; }
     __device__ __forceinline__ float vmin() const { return mn; }
 };
 
-// Two-sum (Knuth) compensated running sum in FP32: s + c carries the prefix
-// with an error of order u^2 per step.  Candidates are s + c evaluated in
-// FP64 (exact for two floats): rounding them to FP32 would cost 2^-24 of the
-// running prefix, which exceeds a 1e-6 relative error once the minimal
-// error is below a few percent.
+// Compensated FP32 running sum.  The sum is carried as s + c with s biased
+// by kKahanBias: s = fl(s + w) tracks kKahanBias + (local prefix), and c
+// collects the exact rounding error of every step.  The local prefix of a
+// lane lies in [-1, 1] (the table's absolute values sum to 1), so s stays in
+// [1, 3] and |w| <= 1 <= |s|: Dekker's Fast2Sum then gives the error of
+// s + w exactly as w - ((s + w) - s), three FP32 operations instead of the
+// six of a sign-agnostic two-sum.  s + c equals the biased prefix up to the
+// rounding of the additions to c, each at most 2^-24 |c|.  Weights below
+// half an ulp of s (2^-23) pass into c whole, so c is folded back into s
+// after every 8 keys (unit_end: one more exact Fast2Sum, |c| < 1 <= |s|),
+// which keeps |c| below about 9 * 2^-23 and each rounding of c below
+// 2^-46.  A candidate is s + c evaluated in FP64
+// (exact for two floats of these magnitudes); rounding it to FP32 would cost
+// 2^-24 of the prefix, more than a 1e-6 relative error once the minimal
+// error is below a few percent.  The split mask is applied to c before its
+// conversion (an integer OR with the all-ones pattern gives a quiet NaN,
+// which the conversion and the FP64 addition carry through), so masking
+// costs one FP32 operation.
+constexpr float kKahanBias = 2.0f;
+
 template <> struct LaneAcc<BOOST_PREC_FP32_KAHAN> {
-    float s = 0.f, c = 0.f;
-    double mx = -4.0, mn = 4.0;
-    __device__ __forceinline__ double add(float w) {
+    float s = kKahanBias, c = 0.f;
+    double mx = (double)kKahanBias - 4.0, mn = (double)kKahanBias + 4.0;
+    __device__ __forceinline__ void key(float w, uint32_t m) {
         const float t = s + w;
-        const float bp = t - s;
-        const float err = (s - (t - bp)) + (w - bp);
+        const float z = t - s;      // exact: |s| >= |w|
+        const float e = w - z;      // exact: the rounding error of s + w
         s = t;
-        c += err;
-        return (double)s + (double)c;
+        c += e;
+        const double v = (double)t + (double)__uint_as_float(__float_as_uint(c) | m);
+        mx = fmax(mx, v);
+        mn = fmin(mn, v);
     }
-    __device__ __forceinline__ void cand(double v, uint32_t m) {
-        const double x = v + nan_or_zero(m);
-        mx = fmax(mx, x);
-        mn = fmin(mn, x);
+    __device__ __forceinline__ void unit_end() {
+        const float t = s + c;
+        const float z = t - s;      // exact: |s| >= 1 > |c|
+        c = c - z;
+        s = t;
     }
-    __device__ __forceinline__ double total() const { return (double)s + (double)c; }
-    __device__ __forceinline__ double vmax() const { return mx; }
-    __device__ __forceinline__ double vmin() const { return mn; }
+    __device__ __forceinline__ double total() const { return ((double)s - (double)kKahanBias) + (double)c; }
+    __device__ __forceinline__ double vmax() const { return mx - (double)kKahanBias; }
+    __device__ __forceinline__ double vmin() const { return mn - (double)kKahanBias; }
 };
 
 template <> struct LaneAcc<BOOST_PREC_FP64> {
     double s = 0.0, mx = -4.0, mn = 4.0;
-    __device__ __forceinline__ double add(double w) { s += w; return s; }
-    __device__ __forceinline__ void cand(double v, uint32_t m) {
-        const double c = v + nan_or_zero(m);
+    __device__ __forceinline__ void key(double w, uint32_t m) {
+        s += w;
+        const double c = s + nan_or_zero(m);
         mx = fmax(mx, c);
         mn = fmin(mn, c);
     }
+    __device__ __forceinline__ void unit_end() {}
     __device__ __forceinline__ double total() const { return s; }
     __device__ __forceinline__ double vmax() const { return mx; }
     __device__ __forceinline__ double vmin() const { return mn; }
@@ -107,12 +133,13 @@ template <> struct LaneAcc<BOOST_PREC_FP64> {
 
 template <> struct LaneAcc<BOOST_PREC_FP32_WIDE> {
     double s = 0.0, mx = -4.0, mn = 4.0;
-    __device__ __forceinline__ double add(float w) { s += (double)w; return s; }
-    __device__ __forceinline__ void cand(double v, uint32_t m) {
-        const double c = v + nan_or_zero(m);
+    __device__ __forceinline__ void key(float w, uint32_t m) {
+        s += (double)w;
+        const double c = s + nan_or_zero(m);
         mx = fmax(mx, c);
         mn = fmin(mn, c);
     }
+    __device__ __forceinline__ void unit_end() {}
     __device__ __forceinline__ double total() const { return s; }
     __device__ __forceinline__ double vmax() const { return mx; }
     __device__ __forceinline__ double vmin() const { return mn; }
@@ -151,8 +178,8 @@ __device__ __forceinline__ void scan_dword(LaneAcc<PREC>& a, const typename Scan
     using Wt = typename ScanTypes<PREC>::W;
     const Wt w0 = tab_lo<Wt, NARROW>(tab, d);
     const Wt w1 = tab_hi<Wt, NARROW>(tab, d);
-    a.cand(a.add(w0), nosplit_lo<NARROW>(d));
-    a.cand(a.add(w1), nosplit_hi<NARROW>(d));
+    a.key(w0, nosplit_lo<NARROW>(d));
+    a.key(w1, nosplit_hi<NARROW>(d));
 }
 
 template <int PREC, bool NARROW>
@@ -161,6 +188,7 @@ __device__ __forceinline__ void scan_unit(LaneAcc<PREC>& a, const typename ScanT
     scan_dword<PREC, NARROW>(a, tab, u.y);
     scan_dword<PREC, NARROW>(a, tab, u.z);
     scan_dword<PREC, NARROW>(a, tab, u.w);
+    a.unit_end();
 }
 
 // Streaming 16-byte load of keys (read once per round; not worth caching).
@@ -328,26 +356,24 @@ __device__ __forceinline__ double weight_sum(const JobDev& jd) {
     return __shfl(p, 0);
 }
 
-// Modes whose running sums are exact: every table value is a multiple of
-// 2^-52 and every prefix has magnitude < 2 (the table's absolute values sum
-// to ~1), so each FP64 partial sum is exactly representable and the result
-// does not depend on the summation order.
-template <int PREC>
-struct ExactSums { static constexpr bool value = PREC == BOOST_PREC_FP32_WIDE || PREC == BOOST_PREC_FP64; };
-
+// Every table value is a multiple of 2^-52 and the table's absolute values
+// sum to about 1, so the FP64 sum of any subset of the table, in any order,
+// is exact: the class totals, every prefix of the FP64 modes' scans, and the
+// update kernel's recomputation of a lane's prefixes.  In the FP32_WIDE and
+// FP64 modes the scan's own sums are therefore exact and order-independent.
 // One entry of the scan's signed weight table: the normalised weight
-// w_i * (1 / S) rounded to the table type (and, in the exact modes, to a
-// multiple of 2^-52: FP32 values of magnitude >= 2^-28 already are one;
-// smaller ones move by at most 2^-53), negated for negatives.
+// w_i * (1 / S) rounded to the table type and to a multiple of 2^-52 (FP32
+// values of magnitude >= 2^-28 already are one; smaller ones move by at most
+// 2^-53), negated for negatives.
 template <int PREC>
 __device__ __forceinline__ typename ScanTypes<PREC>::W table_value(double w, double rS, bool positive) {
     using Wt = typename ScanTypes<PREC>::W;
     constexpr double kGrid = 4503599627370496.0;          // 2^52
     constexpr double kInvGrid = 1.0 / 4503599627370496.0;  // 2^-52
     Wt wn = (Wt)(w * rS);
-    if constexpr (PREC == BOOST_PREC_FP64) {
+    if constexpr (sizeof(Wt) == 8) {
         wn = rint(wn * kGrid) * kInvGrid;
-    } else if constexpr (PREC == BOOST_PREC_FP32_WIDE) {
+    } else {
         if (wn < (Wt)3.7252902984619140625e-9f)           // 2^-28
             wn = (Wt)(rint((double)wn * kGrid) * kInvGrid);
     }

@@ -4,8 +4,13 @@
 // same per-round scratch (workgroup records, the state's sums), so it can be
 // repeated before the first update without changing any result.  The tuner
 // times each candidate on the job's own keys with HIP events and keeps the
-// fastest; results are cached per process by workload shape so that jobs of
-// the same shape are tuned once.
+// fastest; results are cached by workload shape (per process, and in a file
+// when VJBOOST_TUNE_CACHE names one) so that jobs of the same shape are tuned
+// once.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
 #include <map>
 #include <mutex>
 #include <string>
@@ -41,13 +46,71 @@ int time_launches(hipStream_t s, int reps, const std::function<int()>& launch, d
     return rc;
 }
 
+// The cache: in process memory, and, when the environment variable
+// VJBOOST_TUNE_CACHE names a file, also in that file (one "key value ..."
+// line per choice, appended as choices are made; read on the first lookup
+// that misses in memory).  Keys name the device by its architecture and
+// compute-unit count, and the library's schedule table by its size and a
+// revision number, so a file can be shared between processes and boxes of
+// the same kind; a later line for the same key wins.
 static std::mutex g_tune_mu;
 static std::map<std::string, std::vector<int>> g_tune_cache;
+static bool g_file_loaded = false;
+constexpr int kTuneRevision = 2;   // bump when the schedules' meaning changes
+
+static const char* cache_path() {
+    const char* p = getenv("VJBOOST_TUNE_CACHE");
+    return p != nullptr && p[0] != 0 ? p : nullptr;
+}
+
+static void load_file_locked() {
+    if (g_file_loaded) return;
+    g_file_loaded = true;
+    const char* path = cache_path();
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[1024];
+    while (fgets(line, sizeof line, f)) {
+        char* save = nullptr;
+        char* tok = strtok_r(line, " \t\r\n", &save);
+        if (!tok || tok[0] == '#') continue;
+        std::string key = tok;
+        std::vector<int> v;
+        bool ok = true;
+        while ((tok = strtok_r(nullptr, " \t\r\n", &save)) != nullptr) {
+            char* end = nullptr;
+            const long x = strtol(tok, &end, 10);
+            if (end == tok || *end != 0 || x < -1000000 || x > 1000000) { ok = false; break; }
+            v.push_back((int)x);
+        }
+        if (ok && !v.empty()) g_tune_cache[key] = v;
+    }
+    fclose(f);
+}
+
+std::string tune_device_tag(int device) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+        for (char& ch : arch)
+            if (ch == ' ' || ch == '/' || ch == '\t') ch = '_';
+    }
+    return "r" + std::to_string(kTuneRevision) + "/s" + std::to_string(scan_schedule_count()) + "/" + arch + "/" +
+           std::to_string(cus);
+}
 
 bool tune_cache_get(const std::string& key, std::vector<int>& choice) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
-    if (it == g_tune_cache.end()) return false;
+    if (it == g_tune_cache.end()) {
+        load_file_locked();
+        it = g_tune_cache.find(key);
+        if (it == g_tune_cache.end()) return false;
+    }
     choice = it->second;
     return true;
 }
@@ -55,21 +118,37 @@ bool tune_cache_get(const std::string& key, std::vector<int>& choice) {
 void tune_cache_put(const std::string& key, const std::vector<int>& choice) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = choice;
+    const char* path = cache_path();
+    if (!path) return;
+    std::string line = key;
+    for (int v : choice) line += " " + std::to_string(v);
+    line += "\n";
+    FILE* f = fopen(path, "a");   // one short append per choice; a failure only loses persistence
+    if (!f) return;
+    fputs(line.c_str(), f);
+    fclose(f);
 }
 
 void tune_cache_clear() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache.clear();
+    g_file_loaded = false;   // the next miss reads the file again
 }
 
 int tune_single(const JobDev& jd, int precision, int num_cu, int device, hipStream_t s, double* ms_out,
                 int& chosen) {
     const int lanes = jd.g.lanes;
-    const std::string key = "job/" + std::to_string(device) + "/" + std::to_string(precision) + "/" +
+    const std::string key = "job/" + tune_device_tag(device) + "/" + std::to_string(precision) + "/" +
                             std::to_string(lanes) + "/" + std::to_string(jd.g.n) + "/" + std::to_string(jd.F);
     for (int k = 0; k < scan_schedule_count(); ++k) ms_out[k] = -1.0;
     std::vector<int> hit;
-    if (tune_cache_get(key, hit)) { chosen = hit[0]; return BOOST_OK; }
+    ScanPlan probe;
+    if (tune_cache_get(key, hit) && hit.size() == 1 && hit[0] >= 0 && hit[0] < scan_schedule_count() &&
+        scan_schedule_lanes(hit[0]) == lanes &&
+        scan_plan(probe, precision, jd.g.narrow != 0, hit[0], jd.g.n, jd.F, num_cu) == BOOST_OK) {
+        chosen = hit[0];   // a choice from the cache (entries that do not fit are ignored and re-tuned)
+        return BOOST_OK;
+    }
     std::vector<int> ids;
     std::vector<ScanPlan> plans;
     for (int k = 0; k < scan_schedule_count(); ++k) {

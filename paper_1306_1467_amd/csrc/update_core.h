@@ -27,7 +27,6 @@ struct UpdLds {
     double sh[kUpdWg / 64];
     Wt val[kMaxSeg * 8];       // table values of the winning lane's keys, rank order
     uint32_t flags[kMaxSeg];   // run-end flags, one byte per unit
-    double cand[kMaxSeg * 8];  // rounded-sum modes: the lane's candidate values, rank order
     int64_t k;
     int32_t theta;
     int32_t pad;
@@ -99,8 +98,16 @@ __device__ __forceinline__ void update_body(const JobDev& jd, const WgBest* __re
     const int64_t i = (int64_t)part * kUpdWg + tid;
     const int32_t f = i < n ? haar_value(jd.ii, jd.ii_stride, wp1, desc, i) : 0;
     // 2. split rank: the winning lane's segment (table values, run-end flags)
-    // is staged in LDS by the whole workgroup; the running sum is then
-    // recomputed with the scan's arithmetic.
+    // is staged in LDS by the whole workgroup; the lane's prefix at every key
+    // is then computed in parallel (unit sums, a block scan of them, then
+    // within the unit) in FP64, which is exact for the table's values, and
+    // the split is the first run end where that prefix is extreme.  In the
+    // exact modes this is the scan's own value bit for bit.  In the rounded
+    // modes (FP32, compensated FP32) the scan picked the feature, the
+    // polarity and the lane from its rounded sums; within that lane the split
+    // is placed where the exact prefix of the same table is extreme, which
+    // can differ from the scan's choice only among splits whose errors agree
+    // to the scan's rounding.
     const int L = b.lane;
     const int cntL = L >= 0 ? jd.g.q + (L < jd.g.rem ? 1 : 0) : 0;
     for (int u = tid; u < cntL; u += kUpdWg) {
@@ -119,98 +126,50 @@ __device__ __forceinline__ void update_body(const JobDev& jd, const WgBest* __re
     }
     __syncthreads();
     int64_t k = 0;
-    if constexpr (ExactSums<PREC>::value) {
-        // exact running sums: the lane's prefix at every key is computed in
-        // parallel (unit sums, a block scan of them, then within the unit) and
-        // equals the scan's sequential value bit for bit
-        if (L >= 0) {
-            double us[2] = {0.0, 0.0};
+    if (L >= 0) {
+        double us[2] = {0.0, 0.0};
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int u = tid + h * kUpdWg;
-                if (u < cntL)
+        for (int h = 0; h < 2; ++h) {
+            const int u = tid + h * kUpdWg;
+            if (u < cntL)
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) us[h] += (double)lds.val[u * 8 + e];
-            }
-            // exclusive prefix over units: 2 units per thread in order tid, tid + 256
-            const double tsum = us[0];
-            double incl = wave_exclusive_incl(tsum, lane);
-            if (lane == 63) lds.sh[wv] = incl;
-            __syncthreads();
-            double wbase = 0.0, all0 = 0.0;
-            for (int q = 0; q < kUpdWg / 64; ++q) { if (q < wv) wbase += lds.sh[q]; all0 += lds.sh[q]; }
-            double ex0 = wbase + incl - tsum;          // prefix before unit tid
-            __syncthreads();
-            double incl1 = wave_exclusive_incl(us[1], lane);
-            if (lane == 63) lds.sh[wv] = incl1;
-            __syncthreads();
-            double wbase1 = all0;
-            for (int q = 0; q < wv; ++q) wbase1 += lds.sh[q];
-            double ex1 = wbase1 + incl1 - us[1];       // prefix before unit tid + 256
-            // candidates: extreme value, then the smallest rank
-            double best_v = pol > 0 ? -4.0 : 4.0;
-            int best_r = 0x7FFFFFFF;
+                for (int e = 0; e < 8; ++e) us[h] += (double)lds.val[u * 8 + e];
+        }
+        // exclusive prefix over units: 2 units per thread in order tid, tid + 256
+        const double tsum = us[0];
+        double incl = wave_exclusive_incl(tsum, lane);
+        if (lane == 63) lds.sh[wv] = incl;
+        __syncthreads();
+        double wbase = 0.0, all0 = 0.0;
+        for (int q = 0; q < kUpdWg / 64; ++q) { if (q < wv) wbase += lds.sh[q]; all0 += lds.sh[q]; }
+        double ex0 = wbase + incl - tsum;          // prefix before unit tid
+        __syncthreads();
+        double incl1 = wave_exclusive_incl(us[1], lane);
+        if (lane == 63) lds.sh[wv] = incl1;
+        __syncthreads();
+        double wbase1 = all0;
+        for (int q = 0; q < wv; ++q) wbase1 += lds.sh[q];
+        double ex1 = wbase1 + incl1 - us[1];       // prefix before unit tid + 256
+        // candidates: extreme value, then the smallest rank
+        double best_v = pol > 0 ? -4.0 : 4.0;
+        int best_r = 0x7FFFFFFF;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int u = tid + h * kUpdWg;
-                if (u < cntL) {
-                    double acc = h == 0 ? ex0 : ex1;
-                    const uint32_t fr = lds.flags[u];
+        for (int h = 0; h < 2; ++h) {
+            const int u = tid + h * kUpdWg;
+            if (u < cntL) {
+                double acc = h == 0 ? ex0 : ex1;
+                const uint32_t fr = lds.flags[u];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        acc += (double)lds.val[u * 8 + e];
-                        if ((fr >> e) & 1u) {
-                            const bool c = pol > 0 ? acc > best_v : acc < best_v;
-                            if (c) { best_v = acc; best_r = u * 8 + e; }
-                        }
+                for (int e = 0; e < 8; ++e) {
+                    acc += (double)lds.val[u * 8 + e];
+                    if ((fr >> e) & 1u) {
+                        const bool c = pol > 0 ? acc > best_v : acc < best_v;
+                        if (c) { best_v = acc; best_r = u * 8 + e; }
                     }
                 }
             }
-            // block reduction: extreme value, ties to the smaller rank
-#pragma unroll
-            for (int o = 32; o; o >>= 1) {
-                const double ov = __shfl_xor(best_v, o);
-                const int orr = __shfl_xor(best_r, o);
-                const bool c = (pol > 0 ? ov > best_v : ov < best_v) || (ov == best_v && orr < best_r);
-                if (c) { best_v = ov; best_r = orr; }
-            }
-            __syncthreads();
-            if (lane == 0) { lds.wb[wv].eps = best_v; lds.wb[wv].lane = best_r; }
-            __syncthreads();
-            if (tid == 0) {
-                for (int q = 1; q < kUpdWg / 64; ++q) {
-                    const double ov = lds.wb[q].eps;
-                    const int orr = lds.wb[q].lane;
-                    const bool c = (pol > 0 ? ov > best_v : ov < best_v) || (ov == best_v && orr < best_r);
-                    if (c) { best_v = ov; best_r = orr; }
-                }
-                k = 8 * lane_start(jd.g, L) + best_r + 1;
-            }
         }
-    } else if (L >= 0) {
-        // rounded running sums: one thread recomputes the lane's candidate
-        // values in the scan's order (a single dependency chain, no
-        // selection), then the workgroup finds the extreme at a run end and
-        // its first rank
-        if (tid == 0) {
-            LaneAcc<PREC> a;
-            for (int r = 0; r < cntL; ++r) {
-                Wt v8[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) v8[e] = lds.val[r * 8 + e];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) lds.cand[r * 8 + e] = (double)a.add(v8[e]);
-            }
-        }
-        __syncthreads();
-        double best_v = pol > 0 ? -4.0 : 4.0;
-        int best_r = 0x7FFFFFFF;
-        for (int q = tid; q < cntL * 8; q += kUpdWg) {   // ascending per thread: ties keep the first
-            if ((lds.flags[q >> 3] >> (q & 7)) & 1u) {
-                const double v = lds.cand[q];
-                if (pol > 0 ? v > best_v : v < best_v) { best_v = v; best_r = q; }
-            }
-        }
+        // block reduction: extreme value, ties to the smaller rank
 #pragma unroll
         for (int o = 32; o; o >>= 1) {
             const double ov = __shfl_xor(best_v, o);

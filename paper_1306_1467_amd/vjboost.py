@@ -99,6 +99,10 @@ _SIGS = {
     "boost_get_integral": (ctypes.c_int, [_P, _P]),
     "boost_get_sorted": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "boost_classify_train": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
+    "boost_classify_train_curve": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
+    "boost_classify_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
+    "boost_classify": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32,
+                                      _P, _P, _P, _P, _P, ctypes.c_size_t]),
     "boost_destroy": (None, [_P]),
     "boost_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, _P, ctypes.POINTER(Options)]),
     "boost_batch_init": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.POINTER(Options), _P,
@@ -271,6 +275,51 @@ def boost_classify_train(ctx, stumps: np.ndarray, d_out, d_score=None):
                                       _ptr(d_out), _ptr(d_score)))
 
 
+def boost_classify_train_curve(ctx, stumps: np.ndarray, d_curve):
+    stumps = np.ascontiguousarray(stumps, dtype=STUMP_DTYPE)
+    _check(lib().boost_classify_train_curve(ctx, stumps.ctypes.data if len(stumps) else None, len(stumps),
+                                            _ptr(d_curve)))
+
+
+def boost_classify_workspace_bytes(n: int, window_w: int, window_h: int) -> int:
+    return int(lib().boost_classify_workspace_bytes(n, window_w, window_h))
+
+
+def boost_classify(d_images, n: int, window_w: int, window_h: int, d_labels, stumps: np.ndarray, d_out, d_score,
+                   d_curve, stream, d_workspace, workspace_bytes: int):
+    stumps = np.ascontiguousarray(stumps, dtype=STUMP_DTYPE)
+    _check(lib().boost_classify(_ptr(d_images), n, window_w, window_h, _ptr(d_labels),
+                                stumps.ctypes.data if len(stumps) else None, len(stumps), _ptr(d_out), _ptr(d_score),
+                                _ptr(d_curve), stream, _ptr(d_workspace), workspace_bytes))
+
+
+def classify(images, stumps, labels=None, device: str = "cuda:0"):
+    """The strong classifier of the records `stumps` on windows `images`
+    (uint8 [N, H, W], host or device): (decisions uint8 [N], scores float64
+    [N], error curve int32 [T] or None) as torch tensors on the device.  The
+    curve needs labels: entry t - 1 counts the windows the first t stumps
+    misclassify."""
+    torch = _torch()
+    dev = torch.device(device)
+    img = torch.as_tensor(images).to(dev).contiguous()
+    if img.dtype != torch.uint8 or img.dim() != 3:
+        raise ValueError("images must be uint8 [N, H, W]")
+    n, h, w = (int(v) for v in img.shape)
+    lab = None if labels is None else torch.as_tensor(labels).to(dev).contiguous()
+    stumps = np.ascontiguousarray(stumps, dtype=STUMP_DTYPE)
+    T = len(stumps)
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    score = torch.empty(n, dtype=torch.float64, device=dev)
+    curve = torch.empty(max(T, 1), dtype=torch.int32, device=dev) if lab is not None else None
+    ws_bytes = boost_classify_workspace_bytes(n, w, h)
+    if ws_bytes == 0:
+        raise BoostError(BOOST_E_INVALID, "invalid window set")
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    boost_classify(img, n, w, h, lab, stumps, out, score, curve, stream.cuda_stream, ws, ws_bytes)
+    return out, score, (curve[:T] if curve is not None else None)
+
+
 def boost_destroy(ctx):
     if ctx is not None:
         lib().boost_destroy(ctx)
@@ -415,6 +464,14 @@ class Trainer:
         boost_classify_train(self.ctx, stumps, out, score)
         self._sync()
         return out, score
+
+    def error_curve(self, stumps):
+        """Training-error curve: entry t - 1 = training windows misclassified by the first t stumps."""
+        torch = _torch()
+        curve = torch.empty(max(len(stumps), 1), dtype=torch.int32, device=self.device)
+        boost_classify_train_curve(self.ctx, stumps, curve)
+        self._sync()
+        return curve[:len(stumps)]
 
     def timing(self):
         return boost_get_timing(self.ctx)

@@ -56,3 +56,51 @@ def check_stump(gpu, ost, orec, vals, labels, w_norm, n, precision):
         if gpu.threshold != orec.theta:
             e2 = stump_error(vals[gpu.feature], labels, w_norm, gpu.polarity, gpu.threshold)
             assert abs(e2 - best) <= tol
+
+
+# ------------------------------------------------------------ the weight update
+# Section 2.3 step 4 is FP64 on the GPU in every precision mode.  Two checks
+# hold it there:
+#  * given the GPU's own stump and beta, the updated weights follow from the
+#    round's input weights by a handful of FP64 operations on either side
+#    (a product, two normalisations), so they agree to a few units of
+#    2^-53: UPDATE_RTOL.  An update done in FP32 would miss by ~2^-24.
+#  * against the oracle's updated weights, where both picked the same stump
+#    but their betas differ (the scan's error differs within its tolerance):
+#    w_i <- w_i b_i / Z with b_i = beta for correctly classified windows, 1
+#    otherwise.  A change of ln beta moves ln w_i by the same amount for
+#    every correct window and by nothing for the others, and normalising
+#    subtracts one common amount, so the spread of ln(w_gpu / w_oracle) over
+#    the windows grows by at most |ln(beta_gpu / beta_oracle)| per round;
+#    both vectors sum to one, so every |ln(w_gpu / w_oracle)| is at most that
+#    spread (weight_rtol).
+UPDATE_RTOL = 1e-14
+
+
+def updated_weights(vals_j: np.ndarray, labels: np.ndarray, w_norm: np.ndarray, polarity: int, theta: int,
+                    beta: float) -> np.ndarray:
+    """w_i * beta^(1 - e_i), normalised, for the stump (polarity, theta) on
+    feature values vals_j (Section 2.3 step 4 and the next round's step 1)."""
+    h = (polarity * vals_j.astype(np.int64) < polarity * int(theta)).astype(np.int64)
+    correct = h == labels.astype(np.int64)
+    w = np.where(correct, w_norm * beta, w_norm)
+    return w / w.sum()
+
+
+def weight_rtol(betas_gpu, betas_oracle) -> float:
+    """Bound on |w_gpu / w_oracle - 1| after the rounds whose betas are given
+    (same stumps on both sides), plus UPDATE_RTOL per round for rounding."""
+    bg = np.atleast_1d(np.asarray(betas_gpu, dtype=np.float64))
+    bo = np.atleast_1d(np.asarray(betas_oracle, dtype=np.float64))
+    spread = float(np.sum(np.abs(np.log(bg / bo))))
+    return float(np.expm1(spread)) + UPDATE_RTOL * len(bg)
+
+
+def assert_weights(w_gpu: np.ndarray, w_ref: np.ndarray, rtol: float, what: str = ""):
+    """|w_gpu / w_ref - 1| <= rtol where w_ref > 0; exactly 0 where w_ref is 0."""
+    assert np.all(np.isfinite(w_gpu)), what
+    z = w_ref == 0
+    assert np.all(w_gpu[z] == 0), (what, "a zero weight became nonzero", int(np.argmax(w_gpu[z] != 0)))
+    r = np.zeros_like(w_ref)
+    r[~z] = np.abs(w_gpu[~z] / w_ref[~z] - 1.0)
+    assert float(r.max()) <= rtol, (what, float(r.max()), rtol, int(np.argmax(r)))

@@ -112,3 +112,36 @@ def test_stump_layout(vb):
     assert ctypes.sizeof(vb.Stump) == 80
     assert vb.Stump.error_raw.offset == 48
     assert ctypes.sizeof(vb.Options) == 32
+
+
+def test_classify_rejects_bad_arguments_before_device_work(vb):
+    L = vb.lib()
+    assert vb.boost_classify_workspace_bytes(0, 24, 24) == 0
+    assert vb.boost_classify_workspace_bytes(10, 33, 24) == 0
+    assert vb.boost_classify_workspace_bytes(10, 24, 0) == 0
+    assert vb.boost_classify_workspace_bytes(100, 24, 24) >= 625 * 128 * 4
+    fake = ctypes.c_void_p(16)
+    rec = (vb.Stump * 2)()
+    for r in rec:
+        r.type, r.x, r.y, r.cell_w, r.cell_h, r.polarity, r.threshold, r.alpha = 2, 0, 0, 1, 1, 1, 0, 1.0
+    args = lambda **kw: dict(dict(img=fake, n=10, w=24, h=24, lab=None, st=ctypes.cast(rec, ctypes.c_void_p), T=2,
+                                  out=fake, score=None, curve=None, ws=fake, wsb=1 << 30), **kw)
+
+    def call(a):
+        return L.boost_classify(a["img"], a["n"], a["w"], a["h"], a["lab"], a["st"], a["T"], a["out"], a["score"],
+                                a["curve"], None, a["ws"], a["wsb"])
+    assert call(args(img=None)) == vb.BOOST_E_INVALID
+    assert call(args(n=0)) == vb.BOOST_E_INVALID
+    assert call(args(w=33)) == vb.BOOST_E_INVALID
+    assert call(args(T=4097)) == vb.BOOST_E_INVALID
+    assert call(args(st=None)) == vb.BOOST_E_INVALID
+    assert call(args(curve=fake)) == vb.BOOST_E_INVALID          # a curve needs labels
+    assert "labels" in vb.last_error()
+    assert call(args(ws=None)) == vb.BOOST_E_INVALID
+    assert call(args(wsb=10)) == vb.BOOST_E_NOMEM
+    rec[1].cell_w = 13                                             # 2 x 13 > 24: does not fit
+    assert call(args()) == vb.BOOST_E_INVALID
+    rec[1].cell_w = 1
+    rec[0].polarity = 2
+    assert call(args()) == vb.BOOST_E_INVALID
+    assert L.boost_classify_train_curve(None, None, 0, fake) == vb.BOOST_E_INVALID

@@ -92,3 +92,35 @@ def test_batch64_largest_wide_job_with_every_window_size():
     sub = [specs[k] for k in pick]
     data = [s.make() for s in sub]
     _check_jobs(sub, data, [0, 4])
+
+
+@pytest.mark.parametrize("precision", ["fp32_kahan"])
+def test_batch64_every_job_equals_plain(precision):
+    """All 64 jobs of the mixed-window batched workload (windows 16 to 28,
+    1,000 to 8,000 positives and 2,000 to 20,000 negatives per job, 14- and
+    15-bit keys), in its own precision mode and the measured schedule choice:
+    every job's records and weights after 4 batched rounds equal those of the
+    job trained alone, bit for bit."""
+    specs = synth.workload_jobs("batch64")
+    say(f"batch64: generating {len(specs)} jobs")
+    data = [s.make() for s in specs]
+    bt = vb.BatchTrainer([(torch.from_numpy(i), torch.from_numpy(l)) for i, l in data], precision=precision,
+                         schedule_id=vb.BOOST_SCHEDULE_AUTO)
+    say(f"batch64 {precision}: schedules {bt.schedule()}")
+    recs = bt.train(ROUNDS)
+    weights = [bt.weights(k).cpu().numpy() for k in range(len(data))]
+    bt.close()
+    del bt
+    torch.cuda.empty_cache()
+    for k, (images, labels) in enumerate(data):
+        tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=precision,
+                        schedule_id=vb.BOOST_SCHEDULE_AUTO)
+        alone = tr.train(ROUNDS)
+        w_alone = tr.weights().cpu().numpy()
+        tr.close()
+        del tr
+        assert recs[:, k].tobytes() == alone.tobytes(), k
+        assert np.array_equal(weights[k], w_alone), k
+        if k % 16 == 15:
+            say(f"jobs 0..{k} equal alone")
+            torch.cuda.empty_cache()

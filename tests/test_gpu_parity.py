@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_1306_1467_amd import synth
-from tests.helpers import check_stump, err_tolerance
+from tests.helpers import UPDATE_RTOL, assert_weights, check_stump, err_tolerance, updated_weights, weight_rtol
 
 pytestmark = pytest.mark.gpu
 
@@ -98,11 +98,12 @@ def test_rounds_teacher_forced(tiny, precision):
         assert (dn <= tol_n).all(), (t, precision, dn.max(), int(np.argmax(dn - tol_n)))
         check_stump(rec, ost, orec, otr.vals, labels, wn, n, precision)
         assert abs(rec.beta - rec.error / (1 - rec.error)) <= 1e-15 * max(1.0, rec.beta)
+        # the FP64 update of Section 2.3 step 4, from the GPU's own stump and beta
+        w_gpu = tr.weights().cpu().numpy()
+        assert_weights(w_gpu, updated_weights(otr.vals[rec.feature], labels, wn, rec.polarity, rec.threshold,
+                                              rec.beta), UPDATE_RTOL, f"update {precision} {t}")
         if rec.feature == orec.feature and rec.polarity == orec.polarity and rec.threshold == orec.theta:
-            w_gpu = tr.weights().cpu().numpy()
-            w_or = otr.w / otr.w.sum()
-            rtol = 1e-3 if precision == "fp32" else 1e-5
-            assert np.allclose(w_gpu, w_or, rtol=rtol, atol=0)
+            assert_weights(w_gpu, otr.w / otr.w.sum(), weight_rtol(rec.beta, orec.beta), f"oracle {precision} {t}")
         w = otr.w.copy()
     tr.close()
 
@@ -141,6 +142,9 @@ def test_exact_arithmetic_dyadic_weights(tiny, precision):
         assert (rec.feature, rec.polarity, rec.threshold, rec.split_rank) == \
             (orec.feature, orec.polarity, orec.theta, orec.split)
         assert rec.error_raw == orec.err_raw
+        # equal errors give equal betas; the FP64 update then agrees to rounding
+        assert rec.beta == orec.beta and abs(rec.alpha - orec.alpha) <= 1e-15 * max(1.0, abs(orec.alpha))
+        assert_weights(tr.weights().cpu().numpy(), otr_c.w / otr_c.w.sum(), UPDATE_RTOL, f"dyadic {precision}")
         tr.close()
 
 
@@ -235,8 +239,10 @@ def test_shuffled_labels_caller_order():
     orec, ost = otr.round()
     check_stump(rec, ost, orec, otr.vals, labels, ow, len(labels), "fp32_wide")
     w1 = tr.weights().cpu().numpy()
+    assert_weights(w1, updated_weights(otr.vals[rec.feature], labels, ow, rec.polarity, rec.threshold, rec.beta),
+                   UPDATE_RTOL, "shuffled")
     if rec.feature == orec.feature and rec.threshold == orec.theta and rec.polarity == orec.polarity:
-        assert np.allclose(w1, otr.w / otr.w.sum(), rtol=1e-12)
+        assert_weights(w1, otr.w / otr.w.sum(), weight_rtol(rec.beta, orec.beta), "shuffled oracle")
     tr.close()
 
 
@@ -478,6 +484,8 @@ def test_exact_arithmetic_zero_weights_ties(tiny, precision):
     assert (rec.feature, rec.polarity, rec.threshold, rec.split_rank) == \
         (orec.feature, orec.polarity, orec.theta, orec.split)
     assert rec.error_raw == orec.err_raw
+    assert rec.beta == orec.beta
+    assert_weights(tr.weights().cpu().numpy(), otr.w / otr.w.sum(), UPDATE_RTOL, f"zeros {precision}")
     tr.close()
 
 

@@ -27,7 +27,7 @@ import pytest
 
 import oracle
 from paper_1306_1467_amd import synth
-from tests.helpers import U64, stump_error
+from tests.helpers import U64, UPDATE_RTOL, assert_weights, stump_error, updated_weights, weight_rtol
 
 pytestmark = pytest.mark.gpu
 
@@ -151,6 +151,15 @@ def test_precision_teacher_forced(forced, mode):
             assert r_best <= REL, (t, rec.error_raw, orec.err_raw)
             assert same or tie, (t, rec.feature, orec.feature, gap)
             assert float(rel_err(np.array([e_chosen]), np.array([orec.err_raw]), n)[0]) <= REL
+        # the FP64 update (every mode): from the GPU's own stump and beta, and
+        # against the oracle's next weights within the bound its beta allows
+        w_gpu = tr.weights().cpu().numpy()
+        assert_weights(w_gpu, updated_weights(otr.vals[rec.feature], labels, wn, rec.polarity, rec.threshold,
+                                              rec.beta), UPDATE_RTOL, f"update {mode} {t}")
+        if same and t + 1 < len(rounds):
+            rt = weight_rtol(rec.beta, orec.beta)
+            assert_weights(w_gpu, rounds[t + 1][0], rt, f"oracle {mode} {t}")
+            per_round[-1]["weights_rel_bound"] = rt
     tr.close()
     summary = {"mode": mode, "part": "B", "rounds": len(per_round),
                "max_rel_feature": max(r["max_rel_feature"] for r in per_round),

@@ -207,7 +207,76 @@ def test_best_stump_constant_feature():
     v = np.full((1, 5), 7, np.int32)
     st = oracle.best_stumps(v, oracle.sort_features(v), y, w)
     assert abs(st["err_pos"][0] - min(w[y == 1].sum(), w[y == 0].sum())) < 1e-15
-    assert st["split"][0] in (0, 5)
+    # e(+1, 0) = T+ = 0.25 ties e(-1, 5) = T+: p = +1 wins, at the empty split
+    assert (int(st["polarity"][0]), int(st["split"][0]), int(st["theta"][0])) == (1, 0, 7)
+
+
+def _integer_weights(rng, n, zero_frac):
+    """Integer weights (a share of them zero) and the power of two m with
+    sum <= 2^m: the weights k / 2^m are exact in FP64 and so is every sum of
+    them, so equal errors compare equal on the oracle's side too."""
+    k = rng.integers(1, 64, size=n).astype(np.int64)
+    k[rng.random(n) < zero_frac] = 0
+    if k.sum() == 0:
+        k[0] = 1
+    m = int(np.ceil(np.log2(k.sum())))
+    return k, m
+
+
+def _brute_best_split(v, y, k):
+    """The Section 2.3 minimum by brute force with the tie rule (smaller
+    error, then p = +1, then the smaller split rank): every integer theta in
+    [min - 1, max + 1] and both polarities, the error as an exact integer sum
+    of the misclassified weights, and the split rank the threshold realises
+    (p = +1: windows below theta; p = -1: windows at or below theta).
+    Returns (error, p, rank, min error for p = +1, for p = -1, and the ranks
+    other than the chosen one that reach the same minimum for p)."""
+    v = v.astype(np.int64)
+    y = y.astype(np.int64)
+    theta = np.arange(int(v.min()) - 1, int(v.max()) + 2)
+    below = v[None, :] < theta[:, None]                    # [theta, window]
+    at_or_below = v[None, :] <= theta[:, None]
+    e_pos = ((below.astype(np.int64) != y[None, :]) * k[None, :]).sum(axis=1)
+    e_neg = (((~at_or_below).astype(np.int64) != y[None, :]) * k[None, :]).sum(axis=1)
+    r_pos = below.sum(axis=1)
+    r_neg = at_or_below.sum(axis=1)
+    e = min(int(e_pos.min()), int(e_neg.min()))
+    if int(e_pos.min()) == e:
+        p, errs, ranks = 1, e_pos, r_pos
+    else:
+        p, errs, ranks = -1, e_neg, r_neg
+    tied = sorted({int(r) for r in ranks[errs == e]})
+    return e, p, tied[0], int(e_pos.min()), int(e_neg.min()), tied[1:]
+
+
+@pytest.mark.parametrize("seed,n,size,levels,zero_frac", [(0, 24, 5, 2, 0.3), (1, 30, 6, 3, 0.4),
+                                                          (2, 40, 6, 4, 0.0), (3, 17, 4, 2, 0.6)])
+def test_best_stump_tie_rule_smaller_split(seed, n, size, levels, zero_frac):
+    """Z10 reading of the ties: among all minimal-error stumps of a feature,
+    p = +1 before p = -1, then the smallest split rank.  Integer weights with
+    many zeros and a few pixel levels make exactly equal errors at several
+    ranks common; brute force over every threshold decides which one the
+    rule picks, and the oracle's polarity, split rank, threshold and both
+    per-polarity minima must equal it exactly."""
+    images, labels = synth.small_job((110, seed), n, size, levels)
+    rng = np.random.default_rng(111 + seed)
+    k, m = _integer_weights(rng, n, zero_frac)
+    w = k.astype(np.float64) / float(1 << m)
+    feats = oracle.enumerate_features(size, size)
+    vals = oracle.feature_values(oracle.integrals(images), feats)
+    st = oracle.best_stumps(vals, oracle.sort_features(vals), labels, w)
+    ties_at_other_ranks = 0
+    for j in range(len(feats)):
+        e, p, rank, e_pos, e_neg, others = _brute_best_split(vals[j], labels, k)
+        assert st["err_pos"][j] == e_pos / float(1 << m)
+        assert st["err_neg"][j] == e_neg / float(1 << m)
+        assert (int(st["polarity"][j]), int(st["split"][j])) == (p, rank), j
+        # the reported threshold realises that split rank
+        th = int(st["theta"][j])
+        vj = vals[j].astype(np.int64)
+        assert (int(np.sum(vj < th)) if p == 1 else int(np.sum(vj <= th))) == rank
+        ties_at_other_ranks += len(others)
+    assert ties_at_other_ranks > 0   # the rule was exercised
 
 
 def test_sign_flip_invariance():
