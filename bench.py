@@ -1,24 +1,33 @@
 """Benchmark: ms per boosting round of Viola-Jones AdaBoost on one MI355X.
 
-Workload (default): 5,000 + 10,000 synthetic 24x24 windows (seeded stand-in for
-the face / non-face training set), all 162,336 Haar features, FP32 weights
-with FP64 accumulation in the scan.  A step is one boosting round: the scan
-of every feature's sorted keys against the current weights, the argmin over
-features, the threshold, beta / alpha and the weight update.  The one-time
-preparation (integral images, feature values, per-feature sort) runs before
-the timed region and is reported separately as init_ms.
+Headline workload: 5,000 + 10,000 synthetic 24x24 windows (a seeded stand-in
+for the face / non-face training set), all 162,336 Haar features, FP32
+weights scanned with compensated (Kahan-style) FP32 prefix sums -- the
+precision the headline configuration names.  A step is one boosting round:
+the scan of every feature's sorted keys against the current weights, the
+argmin over features, the threshold, beta / alpha and the FP64 weight
+update.  The one-time preparation (integral images, feature values,
+per-feature sort) runs before the timed region and is reported separately
+(init_ms, tuned and with the tuning cache warm).
 
-The scan's launch schedule is the one measured fastest at init (--schedule -1,
-the default) or a fixed one.  Beside the round time the line carries the
-scan's HBM roofline (algorithmic key bytes over its live-measured device
-time, and the copy-calibrated rocprofv3 traffic when it was taken on the same
-code and schedule), a stream probe (the same key reads with no arithmetic),
-the same workload in the other precision modes (FP32 weights with
-compensated FP32 sums, FP64, plain FP32; per-kernel device times over 50
-rounds), the batched-jobs measurement (32 uneven jobs by default,
-jobs*rounds/s, against the same jobs run one at a time through the
-single-job path) and the FP64 oracle's round time on the host cores over 20
-of the 200 rounds.
+Beside the round time the line carries:
+  roofline         the headline scan kernel's algorithmic key bytes over its
+                   live-measured device time against 8 TB/s, and the
+                   copy-calibrated rocprofv3 HBM traffic when a counter record
+                   of the same scan code, precision and schedule is committed;
+  variants         the same workload with FP32 weights accumulated in FP64
+                   (the library's exact mode), with its own roofline;
+  precision_sweep  the FP64 and plain FP32 modes (per-kernel device times);
+  precision_report every mode against the FP64 oracle over K teacher-forced
+                   full-size rounds (every feature, both polarities), on the
+                   headline data and on a non-separable set;
+  batched_*        32 uneven jobs (batch32) and 64 mixed-window jobs (batch64,
+                   in the compensated and the FP64-accumulated modes):
+                   jobs*rounds/s against the same jobs run one at a time;
+  cpu_baseline*    the FP64 oracle timed on the host cores: the headline round
+                   over all features, and bounded samples of both batched
+                   workloads;
+  strong_classifier  training and held-out error of the 200-stump classifier.
 """
 from __future__ import annotations
 
@@ -33,8 +42,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "ms per boosting round (162k Haar × 15k imgs); batched jobs·rounds/s vs plain"
+DTYPE = {"fp32_kahan": "f32", "fp32_wide": "f32 weights, f64 sums", "fp32": "f32", "fp64": "f64"}
+PRECISION_NAME = {"fp32_kahan": "FP32 weights, compensated FP32 prefix sums (Fast2Sum), FP64 candidates",
+                  "fp32_wide": "FP32 weights accumulated in FP64 (exact sums)",
+                  "fp64": "FP64 weights and sums", "fp32": "FP32 weights, plain FP32 sums"}
+
+
 def profiled_traffic(kind: str, precision: str, schedule: int):
-    """HBM bytes per scan launch from the committed rocprofv3 counter summary,
+    """HBM bytes per scan launch from the committed rocprofv3 counter record,
     or None when it is missing or was taken on a different scan source,
     precision or schedule."""
     from paper_1306_1467_amd.profsum import scan_source_hash
@@ -44,46 +59,14 @@ def profiled_traffic(kind: str, precision: str, schedule: int):
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("scan_source_hash") != scan_source_hash() or d.get("precision") != precision:
-        return None
-    return d.get("schedules", {}).get(str(schedule), {}).get("bytes_per_launch")
-
-
-def cpu_baseline(images, labels, n_features: int, rounds: int, rounds_1t: int):
-    """The FP64 oracle's round time on the host cores: `rounds` rounds with
-    every host thread and `rounds_1t` rounds with one thread, over the first
-    `n_features` features (0: all) of the same windows."""
-    import numpy as np
-    import oracle
-    F = oracle.feature_count(24, 24)
-    feats = oracle.enumerate_features(24, 24)
-    nf = F if n_features <= 0 or n_features >= F else n_features
-    pick = np.arange(F) if nf == F else np.sort(np.random.default_rng(0).choice(F, nf, replace=False))
-    threads = oracle.max_threads()
-    t_prep = time.perf_counter()
-    ii = oracle.integrals(images, threads)
-    vals = oracle.feature_values(ii, feats[pick], threads)
-    order = oracle.sort_features(vals, threads)
-    t_prep = time.perf_counter() - t_prep
-    w = oracle.init_weights(labels)
-    scratch = np.zeros(nf, oracle.STUMP_DTYPE)
-    oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)   # warm caches
-    t0 = time.perf_counter()
-    for _ in range(rounds):
-        oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)
-    dt = (time.perf_counter() - t0) / rounds
-    t0 = time.perf_counter()
-    for _ in range(rounds_1t):
-        oracle.boost_round(vals, order, labels, w, 1e-10, 1, scratch)
-    dt1 = (time.perf_counter() - t0) / max(rounds_1t, 1)
-    scale = F / nf
-    what = "all" if nf == F else f"{nf:,} sampled"
-    return {"value": round(dt * 1e3 * scale, 2), "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": f"{rounds} oracle rounds over {what} of {F:,} features x {len(labels):,} windows"
-                      + ("" if nf == F else f", scaled by {scale:.3f}")
-                      + " (one-time value/sort preparation excluded)",
-            "one_thread_ms": round(dt1 * 1e3 * scale, 1), "one_thread_rounds": rounds_1t,
-            "prep_s": round(t_prep * scale, 2), "host_cpu": _cpu_model(), "host_threads": os.cpu_count()}
+    records = d.get("records", [d])
+    h = scan_source_hash()
+    for r in records:
+        if r.get("scan_source_hash") == h and r.get("precision") == precision:
+            got = r.get("schedules", {}).get(str(schedule), {}).get("bytes_per_launch")
+            if got is not None:
+                return got
+    return None
 
 
 def _cpu_model() -> str:
@@ -97,90 +80,161 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def run_single(args, torch, vb, synth):
-    spec = synth.workload_jobs("faces15k")[0]
-    images, labels = spec.make()
-    vb.boost_tune_cache_clear()
+def oracle_tables(images, features=None, threads: int = 0):
+    """The oracle's one-time preparation: values and per-feature orders."""
+    import oracle
+    W = images.shape[2]
+    feats = oracle.enumerate_features(W, images.shape[1]) if features is None else features
     t0 = time.perf_counter()
-    tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=args.precision,
+    ii = oracle.integrals(images, threads)
+    vals = oracle.feature_values(ii, feats, threads)
+    order = oracle.sort_features(vals, threads)
+    return vals, order, time.perf_counter() - t0
+
+
+def cpu_baseline(labels, tables, rounds: int, rounds_1t: int):
+    """The FP64 oracle's round time on the host cores over every feature of
+    the headline workload: `rounds` rounds with every host thread and
+    `rounds_1t` with one thread."""
+    import numpy as np
+    import oracle
+    vals, order, prep_s = tables
+    F, n = vals.shape
+    threads = oracle.max_threads()
+    w = oracle.init_weights(labels)
+    scratch = np.zeros(F, oracle.STUMP_DTYPE)
+    oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)   # warm caches
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)
+    dt = (time.perf_counter() - t0) / rounds
+    t0 = time.perf_counter()
+    for _ in range(rounds_1t):
+        oracle.boost_round(vals, order, labels, w, 1e-10, 1, scratch)
+    dt1 = (time.perf_counter() - t0) / max(rounds_1t, 1)
+    return {"value": round(dt * 1e3, 2), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"{rounds} oracle rounds over all {F:,} features x {n:,} windows "
+                      "(one-time value/sort preparation excluded)",
+            "one_thread_ms": round(dt1 * 1e3, 1), "one_thread_rounds": rounds_1t,
+            "prep_s": round(prep_s, 2), "host_cpu": _cpu_model(), "host_threads": os.cpu_count()}
+
+
+def cpu_baseline_batched(name, specs, data, pick, n_features: int, rounds: int):
+    """The oracle on a bounded sample of a batched workload: the jobs `pick`,
+    each over a seeded sample of n_features features, `rounds` rounds each;
+    every job's round time is scaled by (its feature count / the sample), and
+    the rate is jobs*rounds/s over those jobs.  The whole workload's rate is
+    estimated from the per-key time of the sample."""
+    import numpy as np
+    import oracle
+    threads = oracle.max_threads()
+    t_job = []
+    keys_sampled = 0
+    t_sampled = 0.0
+    for k in pick:
+        images, labels = data[k]
+        s = specs[k]
+        feats = oracle.enumerate_features(s.size, s.size)
+        F = len(feats)
+        nf = min(n_features, F)
+        sel = np.sort(np.random.default_rng(1000 + k).choice(F, nf, replace=False))
+        vals, order, _ = oracle_tables(images, feats[sel], threads)
+        w = oracle.init_weights(labels)
+        scratch = np.zeros(nf, oracle.STUMP_DTYPE)
+        t0 = time.perf_counter()
+        for _ in range(rounds):
+            oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)
+        dt = (time.perf_counter() - t0) / rounds
+        t_job.append(dt * F / nf)
+        keys_sampled += nf * len(labels)
+        t_sampled += dt
+        del vals, order
+    s_per_key = t_sampled / keys_sampled
+    import oracle as _o
+    all_keys = sum(_o.feature_count(s.size, s.size) * s.n for s in specs)
+    return {"value": round(len(pick) / sum(t_job), 3), "unit": "jobs·rounds/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(pick)} of {len(specs)} {name} jobs ({', '.join(str(k) for k in pick)}), "
+                      f"{n_features:,} sampled features each, {rounds} rounds per job, each job's round time "
+                      "scaled by its feature count over the sample",
+            "job_round_s": [round(t, 4) for t in t_job],
+            "est_full_workload_jobs_rounds_per_s": round(len(specs) / (s_per_key * all_keys), 4)}
+
+
+def single_job(args, torch, vb, images, labels, precision: str, steps: int, warmup: int):
+    """One precision mode on the headline workload: init (tuned, and again
+    with the tuning cache warm), the timed graph replay, the per-round
+    distribution, per-kernel device times and the stream probe."""
+    vb.boost_tune_cache_clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=precision,
                     schedule_id=args.schedule)
     torch.cuda.synchronize()
     init_ms = (time.perf_counter() - t0) * 1e3
-    # the schedule in use (under the measured choice: the tuner's pick, timed during init)
     schedule, tune_ms = tr.schedule()
     tuning = {"requested": args.schedule, "chosen": schedule,
               "best_scan_ms_by_schedule": {str(k): round(m, 4) for k, m in enumerate(tune_ms) if m > 0}}
     F, n = tr.F, tr.n
-    if args.warmup:
-        vb.boost_train(tr.ctx, args.warmup, False)
+    if warmup:
+        vb.boost_train(tr.ctx, warmup, False)
     tr.stream.synchronize()
-    # timed region: K rounds replayed from the captured HIP graph; HIP events on
-    # the library's stream bracket the region
+    # timed region: `steps` rounds replayed from the captured HIP graph; HIP
+    # events on the library's stream bracket the region
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(tr.stream):
         ev0.record()
-    vb.boost_train(tr.ctx, args.steps, False)
+    vb.boost_train(tr.ctx, steps, False)
     with torch.cuda.stream(tr.stream):
         ev1.record()
     tr.stream.synchronize()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    graph_ms = ev0.elapsed_time(ev1) / args.steps
-    # per-round distribution (outside the timed region): HIP events around
-    # each single-round graph launch
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    graph_ms = ev0.elapsed_time(ev1) / steps
+    # per-round distribution (outside the timed region)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     with torch.cuda.stream(tr.stream):
         evs[0].record()
-    for r in range(args.steps):
+    for r in range(steps):
         vb.boost_train(tr.ctx, 1, False)
         with torch.cuda.stream(tr.stream):
             evs[r + 1].record()
     tr.stream.synchronize()
-    per_round = sorted(evs[r].elapsed_time(evs[r + 1]) for r in range(args.steps))
+    per_round = sorted(evs[r].elapsed_time(evs[r + 1]) for r in range(steps))
     pct = lambda q: per_round[min(len(per_round) - 1, int(q * len(per_round)))]
-    rec = tr.round()
-    # the strong classifier of 200 stumps on the training windows (outside the timed region)
-    stumps = tr.train(200)
-    tr.classify(stumps)
-    c0 = torch.cuda.Event(enable_timing=True)
-    c1 = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(tr.stream):
-        c0.record()
-    for _ in range(5):
-        tr.classify(stumps)
-    with torch.cuda.stream(tr.stream):
-        c1.record()
-    tr.stream.synchronize()
-    classify_ms = c0.elapsed_time(c1) / 5
-    correct = int((tr.classify(stumps)[0].cpu().numpy() == labels).sum())
     tr.close()
-    # per-kernel device times: the same rounds with HIP events around each
-    # kernel on the library's stream (direct launches)
-    tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=args.precision,
-                    schedule_id=schedule, flags=vb.BOOST_FLAG_TIMING)
-    if args.warmup:
-        vb.boost_train(tr.ctx, args.warmup, False)
+    # init again with the choice in the tuning cache (no timing of candidates)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=precision,
+                    schedule_id=args.schedule, flags=vb.BOOST_FLAG_TIMING)
+    torch.cuda.synchronize()
+    init_hit_ms = (time.perf_counter() - t0) * 1e3
+    # per-kernel device times: HIP events around each kernel (direct launches)
+    if warmup:
+        vb.boost_train(tr.ctx, warmup, False)
     vb.boost_reset_timing(tr.ctx)
     t1 = time.perf_counter()
-    vb.boost_train(tr.ctx, args.steps, False)
+    vb.boost_train(tr.ctx, steps, False)
     tr.stream.synchronize()
-    timed_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    timed_ms = (time.perf_counter() - t1) * 1e3 / steps
     scan_ms, upd_ms, nr, _ = vb.boost_get_timing(tr.ctx)
     probe_ms = vb.boost_probe_stream(tr.ctx, 10)   # the same key reads with no arithmetic
     tr.close()
+    torch.cuda.empty_cache()
     scan_avg = scan_ms / nr
     alg_bytes = F * n * 2
     achieved = alg_bytes / (scan_avg * 1e-3) / 1e9
-    traffic = profiled_traffic("faces15k", args.precision, schedule)
-    out = {
-        "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
+    traffic = profiled_traffic("faces15k", precision, schedule)
+    return {
+        "precision": precision,
+        "ms_per_step": round(elapsed * 1e3 / steps, 4),
         "graph_event_ms_per_round": round(graph_ms, 4),
         "round_ms_p10_p50_p90": [round(pct(0.1), 4), round(pct(0.5), 4), round(pct(0.9), 4)],
         "event_instrumented_ms_per_round": round(timed_ms, 4),
-        "init_ms": round(init_ms, 1),
+        "init_ms": {"tuned": round(init_ms, 1), "tuning_cache_hit": round(init_hit_ms, 1)},
         "scan_ms_avg": round(scan_avg, 4),
         "update_ms_avg": round(upd_ms / nr, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -188,25 +242,19 @@ def run_single(args, torch, vb, synth):
                      "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                                          "copy-calibrated)",
                      "traffic_GBps": None if traffic is None else round(traffic / (scan_avg * 1e-3) / 1e9, 1),
-                     "kernel": f"k_scan (schedule {schedule})", "alg_bytes_per_launch": alg_bytes},
-        "last_round": {"feature": int(rec.feature), "error_raw": rec.error_raw, "polarity": int(rec.polarity),
-                       "threshold": int(rec.threshold)},
-        "strong_classifier": {"stumps": 200, "windows": n, "ms": round(classify_ms, 4),
-                              "training_accuracy": round(correct / n, 4)},
+                     "kernel": f"k_scan<{ {'fp32': 0, 'fp32_kahan': 1, 'fp64': 2, 'fp32_wide': 3}[precision] }, ...> "
+                               f"(schedule {schedule})",
+                     "alg_bytes_per_launch": alg_bytes},
         "stream_probe": {"ms": round(probe_ms, 4), "key_GBps": round(alg_bytes / (probe_ms * 1e-3) / 1e9, 1),
                          "scan_time_over_probe": round(probe_ms / scan_avg, 4)},
-        "schedule_tuning": tuning, "schedule": schedule,
-        "F": F, "n": n,
+        "schedule_tuning": tuning, "schedule": schedule, "F": F, "n": n,
     }
-    return out, images, labels
 
 
-def run_precision_sweep(args, torch, vb, images, labels, F: int, n: int):
-    """The same workload in the other precision modes: per-kernel device
-    times (HIP events around each kernel, direct launches) over a few rounds,
-    each under the measured schedule choice."""
+def run_precision_sweep(args, torch, vb, images, labels, F: int, n: int, modes):
+    """Other precision modes on the same workload: per-kernel device times
+    (HIP events around each kernel, direct launches), measured schedule."""
     out = {}
-    modes = [m for m in args.sweep_precisions.split(",") if m and m != args.precision]
     for prec in modes:
         tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=prec,
                         schedule_id=vb.BOOST_SCHEDULE_AUTO, flags=vb.BOOST_FLAG_TIMING)
@@ -218,6 +266,7 @@ def run_precision_sweep(args, torch, vb, images, labels, F: int, n: int):
         scan_ms, upd_ms, nr, _ = vb.boost_get_timing(tr.ctx)
         tr.close()
         del tr
+        torch.cuda.empty_cache()
         scan_avg = scan_ms / nr
         out[prec] = {"schedule": schedule, "rounds": nr, "scan_ms_avg": round(scan_avg, 4),
                      "update_ms_avg": round(upd_ms / nr, 4), "ms_per_round": round((scan_ms + upd_ms) / nr, 4),
@@ -226,22 +275,79 @@ def run_precision_sweep(args, torch, vb, images, labels, F: int, n: int):
     return out
 
 
-def run_batched(name, args, torch, vb, synth):
-    """Jobs of a batched workload trained together (one scan + one update
-    launch per round for all jobs) against the same jobs trained one at a
-    time through the single-job path, same precision and schedule."""
+def precision_report(torch, vb, datasets, modes, rounds: int):
+    """Every mode against the FP64 oracle over `rounds` teacher-forced rounds
+    per dataset: the oracle runs its own trajectory; each round the GPU gets
+    the oracle's normalised weights, and every feature's two minimal errors,
+    the chosen stump and its error are compared.  Relative errors forgive the
+    oracle's own rounding (4 n 2^-53 absolute); a (0, 0) pair counts 0."""
     import numpy as np
-    specs = synth.workload_jobs(name)
-    data = [s.make() for s in specs]
+    import oracle
+    U64 = 2.0 ** -53
+    out = {}
+    for dname, images, labels, tables in datasets:
+        vals, order, _ = tables
+        n = len(labels)
+        floor = 4.0 * n * U64
+        traj = []
+        w = oracle.init_weights(labels)
+        scratch = np.zeros(vals.shape[0], oracle.STUMP_DTYPE)
+        for _ in range(rounds):
+            wn = w / w.sum()
+            rec, st = oracle.boost_round(vals, order, labels, w, 1e-10, 0, scratch)
+            errs = np.sort(np.partition(st["err"], 1)[:2])
+            traj.append((wn, rec, st["err_pos"].copy(), st["err_neg"].copy(), float(errs[1] - errs[0])))
+
+        def rel(g, r):
+            d = np.maximum(np.abs(g - r) - floor, 0.0)
+            o = np.zeros_like(d)
+            nz = r > 0
+            o[nz] = d[nz] / r[nz]
+            o[~nz] = np.where(d[~nz] > 0, np.inf, 0.0)
+            return o
+        res = {}
+        for mode in modes:
+            tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=mode,
+                            schedule_id=vb.BOOST_SCHEDULE_AUTO)
+            mx_feat, mx_best, agree, ties, mx_abs = 0.0, 0.0, 0, 0, 0.0
+            per_round = []
+            for wn, orec, ep, en, gap in traj:
+                tr.set_weights(wn)
+                g, ferr = tr.round(feature_err=True)
+                ferr = ferr.cpu().numpy()
+                rf = float(max(rel(ferr[:, 0], ep).max(), rel(ferr[:, 1], en).max()))
+                rb = float(rel(np.array([g.error_raw]), np.array([orec.err_raw]))[0])
+                same = (g.feature, g.polarity, g.threshold) == (orec.feature, orec.polarity, orec.theta)
+                tie = gap <= 1e-6 * max(orec.err_raw, floor)
+                mx_feat, mx_best = max(mx_feat, rf), max(mx_best, rb)
+                mx_abs = max(mx_abs, float(max(np.abs(ferr[:, 0] - ep).max(), np.abs(ferr[:, 1] - en).max())))
+                agree += int(same)
+                ties += int((not same) and tie)
+                per_round.append(rf)
+            tr.close()
+            del tr
+            torch.cuda.empty_cache()
+            res[mode] = {"rounds": len(traj), "max_rel_feature_error": mx_feat, "max_rel_best_error": mx_best,
+                         "max_abs_feature_error": mx_abs, "stumps_equal": agree, "differ_at_ties": ties,
+                         "per_round_max_rel_feature_error": per_round}
+        out[dname] = {"windows": n, "features": int(vals.shape[0]),
+                      "eps_range": [min(t[1].err_raw for t in traj), max(t[1].err_raw for t in traj)],
+                      "modes": res}
+    return out
+
+
+def run_batched(name, precision, args, torch, vb, specs, data):
+    """Jobs of a batched workload trained together (persistent scans from a
+    work queue + one update launch per round, graph-replayed) against the same
+    jobs trained one at a time through the single-job path, same precision
+    and schedule policy."""
     rounds = args.batch_rounds or specs[0].rounds
-    prec = args.batch_precision
-    # plain: each job alone; one untimed round first (graph capture), as below
     t_plain = 0.0
     plain = []
     for images, labels in data:
-        tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=prec,
+        tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=precision,
                         schedule_id=args.batch_schedule)
-        vb.boost_train(tr.ctx, 1, False)
+        vb.boost_train(tr.ctx, 1, False)   # graph capture, untimed
         tr.stream.synchronize()
         t0 = time.perf_counter()
         plain.append(vb.boost_train(tr.ctx, rounds, True))
@@ -249,8 +355,9 @@ def run_batched(name, args, torch, vb, synth):
         tr.close()
         del tr
         torch.cuda.empty_cache()
+    vb.boost_tune_cache_clear()
     t0 = time.perf_counter()
-    bt = vb.BatchTrainer([(torch.from_numpy(i), torch.from_numpy(l)) for i, l in data], precision=prec,
+    bt = vb.BatchTrainer([(torch.from_numpy(i), torch.from_numpy(l)) for i, l in data], precision=precision,
                          schedule_id=args.batch_schedule)
     bt.sync()
     init_s = time.perf_counter() - t0
@@ -269,7 +376,7 @@ def run_batched(name, args, torch, vb, synth):
     sizes = sorted({s.size for s in specs})
     return {"workload": f"{len(data)} jobs, " + "/".join(f"{z}x{z}" for z in sizes) + " windows"
                         + f", {min(s.n for s in specs):,}-{max(s.n for s in specs):,} windows per job",
-            "jobs": len(data), "rounds": rounds, "precision": prec, "keys_per_round": keys,
+            "jobs": len(data), "rounds": rounds, "precision": precision, "keys_per_round": keys,
             "batched_jobs_rounds_per_s": round(jr / t_batch, 2),
             "plain_jobs_rounds_per_s": round(jr / t_plain, 2),
             "speedup_vs_plain": round(t_plain / t_batch, 3),
@@ -282,28 +389,71 @@ def run_batched(name, args, torch, vb, synth):
             "stumps_identical_to_plain": bool(same)}
 
 
+def classifier_report(torch, vb, synth, images, labels, precision: str, rounds: int):
+    """The strong classifier of `rounds` stumps: training-error curve and the
+    error on held-out windows of the same recipe (seeded apart)."""
+    import numpy as np
+    tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=precision,
+                    schedule_id=vb.BOOST_SCHEDULE_AUTO)
+    recs = tr.train(rounds)
+    curve = tr.error_curve(recs).cpu().numpy()
+    tr.close()
+    himg, hlab = synth.make_job((1, 1), 1000, 2000)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    _, _, hcurve = vb.classify(himg, recs, hlab)
+    ev1.record()
+    torch.cuda.synchronize()
+    hcurve = hcurve.cpu().numpy()
+    n, m = len(labels), len(hlab)
+    return {"stumps": rounds, "training_windows": n, "held_out_windows": m,
+            "training_error": round(float(curve[-1]) / n, 6), "held_out_error": round(float(hcurve[-1]) / m, 6),
+            "training_error_after_1_10_50": [round(float(curve[t - 1]) / n, 6) for t in (1, 10, 50) if t <= rounds],
+            "held_out_error_after_1_10_50": [round(float(hcurve[t - 1]) / m, 6) for t in (1, 10, 50) if t <= rounds],
+            "held_out_classify_ms": round(ev0.elapsed_time(ev1), 3),
+            "held_out_first_errors": [int(x) for x in hcurve[:5]]}
+
+
+def flipped_job(synth):
+    """A non-separable set of the headline shape: contrast 60, 8 % of the
+    labels flipped by a seeded draw."""
+    import numpy as np
+    images, labels = synth.make_job((25, 0), 5000, 10000, size=24, r0=8, contrast=60.0)
+    flip = np.random.default_rng(25).random(len(labels)) < 0.08
+    return images, np.where(flip, 1 - labels, labels).astype(np.uint8)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", default="fp32_wide")
+    ap.add_argument("--precision", default="fp32_kahan", help="headline precision mode")
+    ap.add_argument("--variants", default="fp32_wide",
+                    help="other modes measured like the headline, with their own roofline (empty: none)")
     ap.add_argument("--schedule", type=int, default=-1,
                     help="scan launch schedule of the single-job workload (-1: measured choice at init)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-features", type=int, default=0, help="oracle features (0: all)")
     ap.add_argument("--cpu-rounds", type=int, default=20)
     ap.add_argument("--cpu-rounds-1t", type=int, default=1)
-    ap.add_argument("--sweep-precisions", default="fp32_kahan,fp64,fp32",
-                    help="other precision modes timed on the same workload (empty: none)")
+    ap.add_argument("--cpu-batch-features", type=int, default=8192,
+                    help="sampled features per job of the batched workloads' oracle baselines")
+    ap.add_argument("--sweep-precisions", default="fp64,fp32",
+                    help="further modes timed on the same workload (empty: none)")
     ap.add_argument("--sweep-rounds", type=int, default=50)
-    ap.add_argument("--batched", default="batch32",
-                    help="comma list of batched workloads to measure (batch32: 32 uneven jobs of 24x24 windows, "
+    ap.add_argument("--precision-rounds", type=int, default=20,
+                    help="teacher-forced full-size rounds per dataset of the precision report (0: none)")
+    ap.add_argument("--batched", default="batch32,batch64",
+                    help="comma list of batched workloads (batch32: 32 uneven jobs of 24x24 windows, "
                          "batch64: 64 jobs of 16-28 px windows); empty for none")
+    ap.add_argument("--batch-precision", default="",
+                    help="modes of the batched runs (comma list; default: the headline mode for batch32, "
+                         "the headline mode and fp32_wide for batch64)")
     ap.add_argument("--batch-rounds", type=int, default=0, help="rounds per batched job (0: the workload's own)")
-    ap.add_argument("--batch-precision", default="fp32_wide")
     ap.add_argument("--batch-schedule", type=int, default=-1,
                     help="schedule of the batched and the plain per-job runs (-1: measured choice at init)")
+    ap.add_argument("--classifier-rounds", type=int, default=200)
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run one device copy of this many GiB first (counter calibration)")
     ap.add_argument("--prep-only", action="store_true",
@@ -327,8 +477,8 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    images, labels = synth.workload_jobs("faces15k")[0].make()
     if args.prep_only:
-        images, labels = synth.workload_jobs("faces15k")[0].make()
         t0 = time.perf_counter()
         tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=args.precision, schedule_id=0)
         torch.cuda.synchronize()
@@ -336,7 +486,7 @@ def main():
                           "features": tr.F, "windows": tr.n}), flush=True)
         tr.close()
         return
-    res, images, labels = run_single(args, torch, vb, synth)
+    res = single_job(args, torch, vb, images, labels, args.precision, args.steps, args.warmup)
     line = {
         "metric": METRIC,
         "value": res["ms_per_step"],
@@ -348,33 +498,65 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32_wide": "f32 weights, f64 accumulation", "fp32_kahan": "f32 two-sum",
-                  "fp32": "f32", "fp64": "f64"}[args.precision],
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": "162,336 Haar features x 15,000 windows 24x24 (5,000 pos + 10,000 neg), "
                                "one boosting round per step", "precision": args.precision,
+                   "precision_detail": PRECISION_NAME[args.precision],
                    "schedule": res["schedule"], "schedule_requested": args.schedule, "features": res["F"],
                    "windows": res["n"]},
-        "init_ms": res["init_ms"],
-        "graph_event_ms_per_round": res["graph_event_ms_per_round"],
-        "round_ms_p10_p50_p90": res["round_ms_p10_p50_p90"],
-        "event_instrumented_ms_per_round": res["event_instrumented_ms_per_round"],
-        "scan_ms_avg": res["scan_ms_avg"],
-        "update_ms_avg": res["update_ms_avg"],
         "roofline": res["roofline"],
-        "last_round": res["last_round"],
-        "stream_probe": res["stream_probe"],
-        "strong_classifier": res["strong_classifier"],
-        "schedule_tuning": res["schedule_tuning"],
     }
-    if args.sweep_precisions:
-        line["precision_sweep"] = run_precision_sweep(args, torch, vb, images, labels, res["F"], res["n"])
-    for name in [c.strip() for c in args.batched.split(",") if c.strip()]:
-        line[f"batched_{name}"] = run_batched(name, args, torch, vb, synth)
+    for k in ("init_ms", "graph_event_ms_per_round", "round_ms_p10_p50_p90", "event_instrumented_ms_per_round",
+              "scan_ms_avg", "update_ms_avg", "stream_probe", "schedule_tuning"):
+        line[k] = res[k]
+    variants = [v.strip() for v in args.variants.split(",") if v.strip() and v.strip() != args.precision]
+    if variants:
+        line["variants"] = {}
+        for v in variants:
+            r = single_job(args, torch, vb, images, labels, v, args.steps, args.warmup)
+            line["variants"][v] = {k: r[k] for k in ("precision", "ms_per_step", "graph_event_ms_per_round",
+                                                     "round_ms_p10_p50_p90", "init_ms", "scan_ms_avg",
+                                                     "update_ms_avg", "roofline", "stream_probe", "schedule")}
+            line["variants"][v]["precision_detail"] = PRECISION_NAME[v]
+    sweep = [m for m in args.sweep_precisions.split(",") if m and m != args.precision and m not in variants]
+    if sweep:
+        line["precision_sweep"] = run_precision_sweep(args, torch, vb, images, labels, res["F"], res["n"], sweep)
+    line["strong_classifier"] = classifier_report(torch, vb, synth, images, labels, args.precision,
+                                                  args.classifier_rounds)
+    headline_tables = None
+    if args.precision_rounds > 0 or not args.no_cpu_baseline:
+        headline_tables = oracle_tables(images)
+    if args.precision_rounds > 0:
+        modes = [args.precision] + [m for m in ("fp32_wide", "fp64", "fp32") if m != args.precision]
+        fimg, flab = flipped_job(synth)
+        line["precision_report"] = precision_report(torch, vb, [("headline", images, labels, headline_tables)],
+                                                    modes, args.precision_rounds)
+        ftables = oracle_tables(fimg)
+        line["precision_report"].update(precision_report(
+            torch, vb, [("contrast60_flipped8pct", fimg, flab, ftables)], modes, args.precision_rounds))
+        del ftables
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(images, labels, args.cpu_features, args.cpu_rounds, args.cpu_rounds_1t)
+        line["cpu_baseline"] = cpu_baseline(labels, headline_tables, args.cpu_rounds, args.cpu_rounds_1t)
     else:
         line["cpu_baseline"] = None
+    del headline_tables
+    for name in [c.strip() for c in args.batched.split(",") if c.strip()]:
+        specs = synth.workload_jobs(name)
+        data = [s.make() for s in specs]
+        if args.batch_precision:
+            modes = [m.strip() for m in args.batch_precision.split(",") if m.strip()]
+        else:
+            modes = [args.precision] + (["fp32_wide"] if name == "batch64" and args.precision != "fp32_wide" else [])
+        for m in modes:
+            key = f"batched_{name}" if m == modes[0] else f"batched_{name}_{m}"
+            line[key] = run_batched(name, m, args, torch, vb, specs, data)
+        if not args.no_cpu_baseline:
+            order = sorted(range(len(specs)), key=lambda k: specs[k].n * vb.boost_feature_count(
+                vb.feature_set(specs[k].size)))
+            pick = list(range(len(specs))) if name == "batch32" else order[:4] + order[-2:]
+            line[f"cpu_baseline_{name}"] = cpu_baseline_batched(name, specs, data, pick, args.cpu_batch_features, 2)
+        del data
     print(json.dumps(line), flush=True)
 
 

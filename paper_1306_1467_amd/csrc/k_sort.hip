@@ -51,17 +51,21 @@ __device__ void bitonic_sort(T* s, int64_t npow2) {
 template <int NT, typename T>
 __device__ void emit_keys(const JobDev& jd, int64_t j, const T* s, int shift, uint64_t imask) {
     const KeyGeom& g = jd.g;
-    const int64_t n = g.n;
+    const int n = (int)g.n;
+    const int nc = (int)g.nc;
+    const int lsh = __builtin_ctz((unsigned)g.lanes);   // lanes per feature: a power of two
     uint4* row = (uint4*)(jd.keys + j * g.row_units);
-    for (int64_t mu = threadIdx.x; mu < g.nc; mu += NT) {
-        const int64_t u = mem_to_unit(g, mu);
+    for (int mu = threadIdx.x; mu < nc; mu += NT) {
+        // memory unit -> rank-order unit (the key layout's lane segments)
+        const int L = mu & (g.lanes - 1);
+        const int u = L * g.q + (L < g.rem ? L : g.rem) + (mu >> lsh);
         uint32_t dw[4];
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
             uint32_t ix[2], fl[2];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                const int64_t r = 8 * u + 2 * h + b;
+                const int r = 8 * u + 2 * h + b;
                 if (r < n) {
                     const T cur = s[r];
                     ix[b] = (uint32_t)((uint64_t)cur & imask);
@@ -215,6 +219,202 @@ __global__ __launch_bounds__(NT) void k_sort(JobDev jd, int64_t npow2, int ib, u
     }
 }
 
+// ---------------------------------------------------------------- counting-sort passes
+// The kernel used for n <= NT * C with C <= 15 (every n up to 15,360).  Thread
+// t owns the C consecutive positions [t C, t C + C) of the current order, so a
+// stable pass is a counting sort in (digit, thread, position-in-thread) order:
+//   1. each thread counts its items' digits in a 64-bit register of 16 packed
+//      4-bit counters (C <= 15, so no field overflows);
+//   2. the counts, spread to 16-bit fields, are scanned across the wave's
+//      lanes (DPP), the waves' totals across (digit, wave) in digit-major
+//      order by one wave, so digit d of thread t starts at
+//      base(d, wave) + (the counts of d in the wave's lower lanes);
+//   3. each thread writes its 16 start offsets to a private LDS row (indexed
+//      by its digits) and scatters its items, in order, to start + (the
+//      number of its earlier items with the same digit), that rank taken from
+//      a second packed running count.
+// Unlike ranking each item among its wave with ballots (several VALU
+// operations per key bit), this costs a few operations per item and pass.
+
+// Inclusive / exclusive scan across the 64 lanes of a wave of four 16-bit
+// counters packed in a 64-bit word (no carries cross fields: every sum stays
+// below 2^16).
+template <int CTRL, int RM, int BM, bool BC>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, RM, BM, BC);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, RM, BM, BC);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ uint64_t wave_scan_incl_u64(uint64_t v) {
+    v += dpp64<0x111, 0xF, 0xF, true>(v);   // row_shr:1
+    v += dpp64<0x112, 0xF, 0xF, true>(v);   // row_shr:2
+    v += dpp64<0x114, 0xF, 0xF, true>(v);   // row_shr:4
+    v += dpp64<0x118, 0xF, 0xF, true>(v);   // row_shr:8
+    v += dpp64<0x142, 0xA, 0xF, false>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp64<0x143, 0xC, 0xF, false>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// Four 4-bit counters (bits 0..15 of x) spread to 16-bit fields.
+__device__ __forceinline__ uint64_t spread4(uint32_t x) {
+    return (uint64_t)(x & 0xFu) | ((uint64_t)((x >> 4) & 0xFu) << 16) | ((uint64_t)((x >> 8) & 0xFu) << 32) |
+           ((uint64_t)((x >> 12) & 0xFu) << 48);
+}
+
+template <int NT, int C>
+struct SortCntLds {
+    uint32_t buf[NT * C];          // the current order (packed words)
+    uint16_t tab[16 * NT];         // tab[d * NT + t]: thread t's start offset of digit d
+    uint64_t wtot[NT / 64][4];     // per wave: the digit totals, 16-bit fields
+    uint16_t base[NT / 64][16];    // per wave: where each digit's run of this wave starts
+    int32_t rmin[NT / 64], rmax[NT / 64];
+};
+
+template <int NT, int C>
+__global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, int ib) {
+    static_assert(C <= 15 && (C & 1) == 1, "4-bit counters; odd C keeps the chunk reads conflict-free");
+    constexpr int NW = NT / 64;
+    static_assert(16 * NW <= 256, "one wave scans the (digit, wave) totals, four per lane");
+    extern __shared__ __align__(16) unsigned char smem[];
+    SortCntLds<NT, C>& L = *reinterpret_cast<SortCntLds<NT, C>*>(smem);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = (int)jd.g.n;
+    const int wp1 = jd.W + 1;
+    // consecutive features run at the same time on the same XCD (workgroups
+    // are dealt to the 8 XCDs in turn), so the integral-image columns they
+    // share are read from that XCD's L2
+    const int G = gridDim.x;
+    const int per_xcd = G / 8;
+    const int slot = G % 8 == 0 ? (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3) : blockIdx.x;
+    for (int64_t j = slot; j < jd.F; j += G) {
+        const uint32_t desc = jd.ftab[j];
+        // 1. values, all loads of a thread in flight together
+        int32_t v[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int i = k * NT + tid;
+            v[k] = i < n ? haar_value(jd.ii, jd.ii_stride, wp1, desc, i) : 0;
+        }
+        int32_t vmin = INT_MAX, vmax = INT_MIN;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int i = k * NT + tid;
+            if (i < n) {
+                vmin = v[k] < vmin ? v[k] : vmin;
+                vmax = v[k] > vmax ? v[k] : vmax;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o; o >>= 1) {
+            const int32_t a = __shfl_xor(vmin, o), b = __shfl_xor(vmax, o);
+            vmin = a < vmin ? a : vmin;
+            vmax = b > vmax ? b : vmax;
+        }
+        if (lane == 0) { L.rmin[wv] = vmin; L.rmax[wv] = vmax; }
+        __syncthreads();
+        vmin = L.rmin[0]; vmax = L.rmax[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+            vmin = L.rmin[w] < vmin ? L.rmin[w] : vmin;
+            vmax = L.rmax[w] > vmax ? L.rmax[w] : vmax;
+        }
+        const uint32_t range = (uint32_t)(vmax - vmin);
+        const int rb = range == 0 ? 0 : 32 - __clz(range);   // <= 18 for windows up to 32x32, ib <= 14
+        // packed words in index order; positions past n hold all-ones
+        // sentinels (digit 15 in every pass, behind every window)
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int i = k * NT + tid;
+            L.buf[i] = i < n ? (((uint32_t)(v[k] - vmin)) << ib) | (uint32_t)i : 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        uint32_t it[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) it[k] = L.buf[tid * C + k];
+        for (int sh = ib; sh < ib + rb; sh += 4) {
+            // 1. counts
+            uint64_t cnt = 0;
+#pragma unroll
+            for (int k = 0; k < C; ++k) cnt += 1ull << (4 * ((it[k] >> sh) & 15u));
+            // 2. scan across the wave, then across (digit, wave)
+            uint64_t f[4], ex[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                f[q] = spread4((uint32_t)(cnt >> (16 * q)) & 0xFFFFu);
+                const uint64_t inc = wave_scan_incl_u64(f[q]);
+                ex[q] = inc - f[q];
+                if (lane == 63) L.wtot[wv][q] = inc;
+            }
+            __syncthreads();   // also: every thread has read its chunk of the previous order
+            if (wv == 0) {
+                // (digit, wave) entries x = d * NW + w in digit-major order, four per lane
+                uint32_t e[4], sum = 0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int x = 4 * lane + a;
+                    const int d = x / NW, w = x % NW;
+                    e[a] = x < 16 * NW ? (uint32_t)((L.wtot[w][d >> 2] >> (16 * (d & 3))) & 0xFFFFu) : 0u;
+                    sum += e[a];
+                }
+                uint32_t incl = sum;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(incl, o);
+                    if (lane >= o) incl += y;
+                }
+                uint32_t run = incl - sum;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int x = 4 * lane + a;
+                    if (x < 16 * NW) L.base[x % NW][x / NW] = (uint16_t)run;
+                    run += e[a];
+                }
+            }
+            __syncthreads();
+            // 3. this thread's start offsets, then the scatter
+#pragma unroll
+            for (int d = 0; d < 16; ++d)
+                L.tab[d * NT + tid] = (uint16_t)(L.base[wv][d] + (uint32_t)((ex[d >> 2] >> (16 * (d & 3))) & 0xFFFFu));
+            uint64_t run = 0;
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                const uint32_t d = (it[k] >> sh) & 15u;
+                const uint32_t r = (uint32_t)(run >> (4 * d)) & 15u;
+                run += 1ull << (4 * d);
+                L.buf[L.tab[d * NT + tid] + r] = it[k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < C; ++k) it[k] = L.buf[tid * C + k];
+        }
+        __syncthreads();
+        emit_keys<NT, uint32_t>(jd, j, L.buf, ib, (1u << ib) - 1u);
+        __syncthreads();
+    }
+}
+
+template <int NT, int C>
+static int sort_cnt_launch(const JobDev& jd, int num_cu, hipStream_t s) {
+    const int64_t n = jd.g.n;
+    int ib = n <= 1 ? 1 : 32 - __builtin_clz((unsigned)(n - 1));
+    const size_t lds = sizeof(SortCntLds<NT, C>);
+    const void* k = (const void*)k_sort_cnt<NT, C>;
+    VJB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    VJB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, NT, lds));
+    if (per_cu < 1) {
+        set_error("sort kernel does not fit on a compute unit");
+        return BOOST_E_INVALID;
+    }
+    int64_t grid = (int64_t)per_cu * num_cu;
+    if (grid > jd.F) grid = jd.F;
+    if (grid > kMaxSortGrid) grid = kMaxSortGrid;
+    JobDev a = jd;
+    void* args[] = {(void*)&a, (void*)&ib};
+    VJB_HIP(hipLaunchKernel(k, dim3((unsigned)grid), dim3(NT), args, lds, s));
+    return BOOST_OK;
+}
+
 template <int NT, int C>
 static int sort_launch_c(const JobDev& jd, uint64_t* scratch, int num_cu, hipStream_t s) {
     const int64_t n = jd.g.n;
@@ -242,9 +442,15 @@ static int sort_launch_c(const JobDev& jd, uint64_t* scratch, int num_cu, hipStr
     return BOOST_OK;
 }
 
-// C values per thread: the smallest that covers n (n <= 32767).
+// Counting-sort passes up to 15,360 windows (C values per thread, the
+// smallest odd C of the shape that covers n); ballot-ranked passes beyond.
 int sort_launch(const JobDev& jd, uint64_t* scratch, int num_cu, hipStream_t s) {
     const int64_t n = jd.g.n;
+    if (n <= 256 * 7) return sort_cnt_launch<256, 7>(jd, num_cu, s);
+    if (n <= 512 * 7) return sort_cnt_launch<512, 7>(jd, num_cu, s);
+    if (n <= 1024 * 7) return sort_cnt_launch<1024, 7>(jd, num_cu, s);
+    if (n <= 1024 * 11) return sort_cnt_launch<1024, 11>(jd, num_cu, s);
+    if (n <= 1024 * 15) return sort_cnt_launch<1024, 15>(jd, num_cu, s);
     if (n <= 256) return sort_launch_c<256, 1>(jd, scratch, num_cu, s);
     if (n <= 512) return sort_launch_c<256, 2>(jd, scratch, num_cu, s);
     if (n <= 1024) return sort_launch_c<256, 4>(jd, scratch, num_cu, s);

@@ -109,20 +109,20 @@ struct RingScan {
             const uint4* base = pf + rr * LPF;
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
-                if (!LAST || k < last) scan_unit<PREC, NARROW>(a, tab, u[k]);
+                if (!LAST || k < last) scan_unit<PREC, NARROW>(a, tab, u[k], (k & 1) != 0);
                 u[k] = ld_stream(base + k * LPF);
             }
         } else if (fill_live) {
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
-                if (!LAST || k < last) scan_unit<PREC, NARROW>(a, tab, u[k]);
+                if (!LAST || k < last) scan_unit<PREC, NARROW>(a, tab, u[k], (k & 1) != 0);
                 const int r = rr + k;
                 u[k] = ld_stream(r < cf ? pf + r * LPF : jd.pad);
             }
         } else {   // nothing left to load: the wave's last batch
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k)
-                if (!LAST || k < last) scan_unit<PREC, NARROW>(a, tab, u[k]);
+                if (!LAST || k < last) scan_unit<PREC, NARROW>(a, tab, u[k], (k & 1) != 0);
         }
         advance_fill(jd);
     }
@@ -169,7 +169,7 @@ __device__ __forceinline__ WgBest scan_range(const JobDev& jd, const typename Sc
                                              double2* __restrict__ ferr) {
     constexpr int G = 64 / LPF;
     constexpr int H = UNROLL / 2;
-    static_assert(RING || UNROLL % 2 == 0, "the tail batch is half a batch");
+    static_assert(UNROLL % 2 == 0, "batches of an even number of units (the tail batch is half a batch)");
     const int lane = threadIdx.x & 63;
     const int grp = lane / LPF, L = lane % LPF;
     const int cnt = jd.g.q + (L < jd.g.rem ? 1 : 0);
@@ -206,16 +206,16 @@ __device__ __forceinline__ WgBest scan_range(const JobDev& jd, const typename Sc
     while (true) {
         LaneAcc<PREC> a;
 #pragma unroll
-        for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
+        for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k], (k & 1) != 0);
         for (int b = 1; b < nbf; ++b) {
             load_batch<UNROLL>(u, p, stride, b, nb, stride ? cnt : 0, jd.pad);
 #pragma unroll
-            for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
+            for (int k = 0; k < UNROLL; ++k) scan_unit<PREC, NARROW>(a, tab, u[k], (k & 1) != 0);
         }
         if (half) {
             load_tail<H>(u, p, stride, nbf * UNROLL, stride ? cnt : 0, jd.pad);
 #pragma unroll
-            for (int k = 0; k < H; ++k) scan_unit<PREC, NARROW>(a, tab, u[k]);
+            for (int k = 0; k < H; ++k) scan_unit<PREC, NARROW>(a, tab, u[k], (k & 1) != 0);
         }
         const int64_t jcur = j;
         t += nsteps;

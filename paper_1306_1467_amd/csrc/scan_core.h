@@ -82,9 +82,9 @@ template <> struct LaneAcc<BOOST_PREC_FP32> {
 // six of a sign-agnostic two-sum.  s + c equals the biased prefix up to the
 // rounding of the additions to c, each at most 2^-24 |c|.  Weights below
 // half an ulp of s (2^-23) pass into c whole, so c is folded back into s
-// after every 8 keys (unit_end: one more exact Fast2Sum, |c| < 1 <= |s|),
-// which keeps |c| below about 9 * 2^-23 and each rounding of c below
-// 2^-46.  A candidate is s + c evaluated in FP64
+// after every 16 keys (unit_end: one more exact Fast2Sum, |c| < 1 <= |s|),
+// which keeps |c| below about 17 * 2^-23 and each rounding of c below
+// 2^-45.  A candidate is s + c evaluated in FP64
 // (exact for two floats of these magnitudes); rounding it to FP32 would cost
 // 2^-24 of the prefix, more than a 1e-6 relative error once the minimal
 // error is below a few percent.  The split mask is applied to c before its
@@ -182,13 +182,19 @@ __device__ __forceinline__ void scan_dword(LaneAcc<PREC>& a, const typename Scan
     a.key(w1, nosplit_hi<NARROW>(d));
 }
 
+// One unit (8 keys).  The compensated mode folds its correction back into
+// the running sum after every odd unit of a lane's segment (unit index r odd):
+// every load discipline scans a lane's units in order with batches of an even
+// length starting at even r, so the odd-k units of a batch are exactly the
+// odd-r units, and the results do not depend on the schedule.
 template <int PREC, bool NARROW>
-__device__ __forceinline__ void scan_unit(LaneAcc<PREC>& a, const typename ScanTypes<PREC>::W* tab, const uint4& u) {
+__device__ __forceinline__ void scan_unit(LaneAcc<PREC>& a, const typename ScanTypes<PREC>::W* tab, const uint4& u,
+                                          bool odd) {
     scan_dword<PREC, NARROW>(a, tab, u.x);
     scan_dword<PREC, NARROW>(a, tab, u.y);
     scan_dword<PREC, NARROW>(a, tab, u.z);
     scan_dword<PREC, NARROW>(a, tab, u.w);
-    a.unit_end();
+    if (odd) a.unit_end();
 }
 
 // Streaming 16-byte load of keys (read once per round; not worth caching).

@@ -93,19 +93,23 @@ def counters(fetch_csv: str, write_csv: str, copy_gib: float, kernel: str, preci
            "write_bytes_per_launch": round(write_b), "fetch_counter_per_byte": ff, "write_counter_per_byte": wf,
            "copy_bytes": copy_bytes, "launches": [len(fk), len(wk)]}
     if json_out:
-        # one record per schedule; records of other schedules are kept while
-        # the scan sources and the precision are unchanged
-        doc = {"scan_source_hash": scan_source_hash(), "precision": precision, "schedules": {}}
+        # one record per (precision, scan source), holding one entry per
+        # schedule; records taken on other scan sources are dropped
+        h = scan_source_hash()
+        records = []
         try:
             with open(json_out) as f:
                 old = json.load(f)
-            if old.get("scan_source_hash") == doc["scan_source_hash"] and old.get("precision") == precision:
-                doc["schedules"].update(old.get("schedules", {}))
+            records = [r for r in old.get("records", [old]) if r.get("scan_source_hash") == h]
         except (OSError, ValueError):
             pass
-        doc["schedules"][str(schedule)] = rec
+        this = next((r for r in records if r.get("precision") == precision), None)
+        if this is None:
+            this = {"scan_source_hash": h, "precision": precision, "schedules": {}}
+            records.append(this)
+        this["schedules"][str(schedule)] = rec
         with open(json_out, "w") as f:
-            json.dump(doc, f, indent=1)
+            json.dump({"records": records}, f, indent=1)
             f.write("\n")
     lines = ["# HBM traffic per launch of `" + kernel + "`", "",
              "FETCH_SIZE pass:", "", "```", cmd_fetch, "```", "", "WRITE_SIZE pass:", "", "```", cmd_write, "```", "",

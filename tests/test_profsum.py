@@ -42,7 +42,9 @@ def test_counters_are_scaled_by_the_copy(tmp_path):
     out = tmp_path / "rec.json"
     text = profsum.counters(fetch, write, gib, r"k_scan<3, true, 512, 4, 16, true>", "fp32_wide", 9, "cf", "cw",
                             str(out), 4096000)
-    rec = json.load(open(out))
+    doc = json.load(open(out))
+    assert len(doc["records"]) == 1
+    rec = doc["records"][0]
     r9 = rec["schedules"]["9"]
     # mean fetch 2000 KiB at 0.5 counter bytes per byte -> 4,096,000 bytes; write 10 KiB at 1.0
     assert r9["fetch_bytes_per_launch"] == 4096000
@@ -51,12 +53,20 @@ def test_counters_are_scaled_by_the_copy(tmp_path):
     assert r9["launches"] == [2, 1]
     assert rec["scan_source_hash"] == profsum.scan_source_hash() and rec["precision"] == "fp32_wide"
     assert "measured / algorithmic = 1.0025" in text
-    # a second schedule is added beside the first; another precision starts over
+    # a second schedule is added beside the first; another precision gets a record of its own
     profsum.counters(fetch, write, gib, r"k_scan<3, true, 512, 4, 16, true>", "fp32_wide", 3, "cf", "cw", str(out),
                      None)
-    assert sorted(json.load(open(out))["schedules"]) == ["3", "9"]
+    assert sorted(json.load(open(out))["records"][0]["schedules"]) == ["3", "9"]
     profsum.counters(fetch, write, gib, r"k_scan<3, true, 512, 4, 16, true>", "fp64", 3, "cf", "cw", str(out), None)
-    assert sorted(json.load(open(out))["schedules"]) == ["3"]
+    recs = {r["precision"]: r for r in json.load(open(out))["records"]}
+    assert sorted(recs) == ["fp32_wide", "fp64"] and sorted(recs["fp64"]["schedules"]) == ["3"]
+    # a record of other scan sources is dropped
+    doc = json.load(open(out))
+    doc["records"][0]["scan_source_hash"] = "stale"
+    json.dump(doc, open(out, "w"))
+    profsum.counters(fetch, write, gib, r"k_scan<3, true, 512, 4, 16, true>", "fp64", 9, "cf", "cw", str(out), None)
+    recs = {r["precision"]: r for r in json.load(open(out))["records"]}
+    assert sorted(recs) == ["fp64"] and sorted(recs["fp64"]["schedules"]) == ["3", "9"]
 
 
 def test_counters_need_the_copy_and_the_kernel(tmp_path):
@@ -94,17 +104,20 @@ def test_committed_counter_record_matches_the_scan_sources():
     code: a record whose source hash matches is used as committed, a stale
     one never."""
     path = os.path.join(ROOT, "profiles", "stump_scan_faces15k_counters.json")
-    rec = json.load(open(path))
+    doc = json.load(open(path))
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
-    current = rec["scan_source_hash"] == profsum.scan_source_hash()
-    for s, r in rec["schedules"].items():
-        got = bench.profiled_traffic("faces15k", rec["precision"], int(s))
-        if current:
-            assert got == r["bytes_per_launch"]
-            assert 1.0 <= r["bytes_per_launch"] / 4870080000 < 1.01
-        else:
-            assert got is None
-    other = "fp64" if rec["precision"] != "fp64" else "fp32"
+    precisions = set()
+    for rec in doc.get("records", [doc]):
+        current = rec["scan_source_hash"] == profsum.scan_source_hash()
+        precisions.add(rec["precision"])
+        for s, r in rec["schedules"].items():
+            got = bench.profiled_traffic("faces15k", rec["precision"], int(s))
+            if current:
+                assert got == r["bytes_per_launch"]
+                assert 1.0 <= r["bytes_per_launch"] / 4870080000 < 1.01
+            else:
+                assert got is None
+    other = next(p for p in ("fp64", "fp32", "fp32_wide", "fp32_kahan") if p not in precisions)
     assert bench.profiled_traffic("faces15k", other, 9) is None
