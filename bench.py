@@ -69,6 +69,11 @@ def profiled_traffic(kind: str, precision: str, schedule: int):
     return None
 
 
+def progress(msg: str):
+    """One line per finished step on stderr (the JSON result line is the only stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -81,6 +86,7 @@ def _cpu_model() -> str:
 
 
 def oracle_tables(images, features=None, threads: int = 0):
+    # threads: OpenMP threads of every oracle call (0: the current setting)
     """The oracle's one-time preparation: values and per-feature orders."""
     import oracle
     W = images.shape[2]
@@ -92,15 +98,14 @@ def oracle_tables(images, features=None, threads: int = 0):
     return vals, order, time.perf_counter() - t0
 
 
-def cpu_baseline(labels, tables, rounds: int, rounds_1t: int):
+def cpu_baseline(labels, tables, rounds: int, rounds_1t: int, threads: int):
     """The FP64 oracle's round time on the host cores over every feature of
-    the headline workload: `rounds` rounds with every host thread and
+    the headline workload: `rounds` rounds with `threads` host threads and
     `rounds_1t` with one thread."""
     import numpy as np
     import oracle
     vals, order, prep_s = tables
     F, n = vals.shape
-    threads = oracle.max_threads()
     w = oracle.init_weights(labels)
     scratch = np.zeros(F, oracle.STUMP_DTYPE)
     oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)   # warm caches
@@ -119,7 +124,7 @@ def cpu_baseline(labels, tables, rounds: int, rounds_1t: int):
             "prep_s": round(prep_s, 2), "host_cpu": _cpu_model(), "host_threads": os.cpu_count()}
 
 
-def cpu_baseline_batched(name, specs, data, pick, n_features: int, rounds: int):
+def cpu_baseline_batched(name, specs, data, pick, n_features: int, rounds: int, threads: int):
     """The oracle on a bounded sample of a batched workload: the jobs `pick`,
     each over a seeded sample of n_features features, `rounds` rounds each;
     every job's round time is scaled by (its feature count / the sample), and
@@ -127,7 +132,6 @@ def cpu_baseline_batched(name, specs, data, pick, n_features: int, rounds: int):
     estimated from the per-key time of the sample."""
     import numpy as np
     import oracle
-    threads = oracle.max_threads()
     t_job = []
     keys_sampled = 0
     t_sampled = 0.0
@@ -275,7 +279,7 @@ def run_precision_sweep(args, torch, vb, images, labels, F: int, n: int, modes):
     return out
 
 
-def precision_report(torch, vb, datasets, modes, rounds: int):
+def precision_report(torch, vb, datasets, modes, rounds: int, threads: int = 0):
     """Every mode against the FP64 oracle over `rounds` teacher-forced rounds
     per dataset: the oracle runs its own trajectory; each round the GPU gets
     the oracle's normalised weights, and every feature's two minimal errors,
@@ -294,7 +298,7 @@ def precision_report(torch, vb, datasets, modes, rounds: int):
         scratch = np.zeros(vals.shape[0], oracle.STUMP_DTYPE)
         for _ in range(rounds):
             wn = w / w.sum()
-            rec, st = oracle.boost_round(vals, order, labels, w, 1e-10, 0, scratch)
+            rec, st = oracle.boost_round(vals, order, labels, w, 1e-10, threads, scratch)
             errs = np.sort(np.partition(st["err"], 1)[:2])
             traj.append((wn, rec, st["err_pos"].copy(), st["err_neg"].copy(), float(errs[1] - errs[0])))
 
@@ -478,6 +482,10 @@ def main():
         torch.cuda.synchronize()
         del a, b
     images, labels = synth.workload_jobs("faces15k")[0].make()
+    host_threads = 0
+    if not args.no_cpu_baseline or args.precision_rounds > 0:
+        import oracle
+        host_threads = oracle.max_threads()   # every host thread; the oracle calls below pass it explicitly
     if args.prep_only:
         t0 = time.perf_counter()
         tr = vb.Trainer(torch.from_numpy(images), torch.from_numpy(labels), precision=args.precision, schedule_id=0)
@@ -487,6 +495,7 @@ def main():
         tr.close()
         return
     res = single_job(args, torch, vb, images, labels, args.precision, args.steps, args.warmup)
+    progress(f"headline {args.precision}: {res['ms_per_step']} ms per round")
     line = {
         "metric": METRIC,
         "value": res["ms_per_step"],
@@ -519,25 +528,32 @@ def main():
                                                      "round_ms_p10_p50_p90", "init_ms", "scan_ms_avg",
                                                      "update_ms_avg", "roofline", "stream_probe", "schedule")}
             line["variants"][v]["precision_detail"] = PRECISION_NAME[v]
+            progress(f"variant {v}: {r['ms_per_step']} ms per round")
     sweep = [m for m in args.sweep_precisions.split(",") if m and m != args.precision and m not in variants]
     if sweep:
         line["precision_sweep"] = run_precision_sweep(args, torch, vb, images, labels, res["F"], res["n"], sweep)
+        progress("precision sweep done")
     line["strong_classifier"] = classifier_report(torch, vb, synth, images, labels, args.precision,
                                                   args.classifier_rounds)
+    progress("strong classifier done")
     headline_tables = None
     if args.precision_rounds > 0 or not args.no_cpu_baseline:
-        headline_tables = oracle_tables(images)
+        headline_tables = oracle_tables(images, None, host_threads)
+        progress("oracle tables of the headline data built")
     if args.precision_rounds > 0:
         modes = [args.precision] + [m for m in ("fp32_wide", "fp64", "fp32") if m != args.precision]
         fimg, flab = flipped_job(synth)
         line["precision_report"] = precision_report(torch, vb, [("headline", images, labels, headline_tables)],
-                                                    modes, args.precision_rounds)
-        ftables = oracle_tables(fimg)
+                                                    modes, args.precision_rounds, host_threads)
+        progress("precision report: headline data done")
+        ftables = oracle_tables(fimg, None, host_threads)
         line["precision_report"].update(precision_report(
-            torch, vb, [("contrast60_flipped8pct", fimg, flab, ftables)], modes, args.precision_rounds))
+            torch, vb, [("contrast60_flipped8pct", fimg, flab, ftables)], modes, args.precision_rounds, host_threads))
         del ftables
+        progress("precision report: flipped-label data done")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(labels, headline_tables, args.cpu_rounds, args.cpu_rounds_1t)
+        line["cpu_baseline"] = cpu_baseline(labels, headline_tables, args.cpu_rounds, args.cpu_rounds_1t, host_threads)
+        progress("oracle baseline of the headline round done")
     else:
         line["cpu_baseline"] = None
     del headline_tables
@@ -551,11 +567,14 @@ def main():
         for m in modes:
             key = f"batched_{name}" if m == modes[0] else f"batched_{name}_{m}"
             line[key] = run_batched(name, m, args, torch, vb, specs, data)
+            progress(f"{name} {m}: {line[key]['speedup_vs_plain']}x plain")
         if not args.no_cpu_baseline:
             order = sorted(range(len(specs)), key=lambda k: specs[k].n * vb.boost_feature_count(
                 vb.feature_set(specs[k].size)))
             pick = list(range(len(specs))) if name == "batch32" else order[:4] + order[-2:]
-            line[f"cpu_baseline_{name}"] = cpu_baseline_batched(name, specs, data, pick, args.cpu_batch_features, 2)
+            line[f"cpu_baseline_{name}"] = cpu_baseline_batched(name, specs, data, pick, args.cpu_batch_features, 2,
+                                                                host_threads)
+            progress(f"oracle baseline of {name} done")
         del data
     print(json.dumps(line), flush=True)
 

@@ -193,6 +193,32 @@ int boost_init(boost_ctx **out, const uint8_t *d_images, const uint8_t *d_labels
                const boost_feature_set *fs, const boost_options *o,
                void *d_workspace, size_t workspace_bytes);
 
+/* Incremental retraining: a new context over the union of c's windows (in
+ * c's caller order) and m new ones (after them), as boost_init would prepare
+ * it from the concatenated images and labels -- bit for bit the same
+ * integral images, feature values, sorted keys and initial weights (Table 2
+ * over the union), so training continues as from a fresh boost_init.  The
+ * paper's case for a distributed trainer is fast retraining when the
+ * training set changes (Abstract, Section 1.1); here the old windows' value
+ * order is reused: only the new windows are sorted and merged into each
+ * feature's order (unions up to 15,360 windows; larger ones are sorted in
+ * full), the old windows' integral images are copied.
+ *   c              a prepared context (not modified; it stays valid).
+ *   d_images       m new windows, window_h x window_w uint8 row-major (device).
+ *   d_labels       m labels 0/1 (device).
+ *   d_workspace    caller-owned device memory of at least
+ *                  boost_extend_workspace_bytes(c, m) bytes (that of
+ *                  boost_workspace_bytes for n + m windows), distinct from c's.
+ * The new context has c's feature set and options (precision, schedule
+ * policy, stream, ...).  Errors as boost_init, and BOOST_E_INVALID for m < 1
+ * or n + m > 32767.  Synchronises.
+ * boost_extend_merged: 1 if the context's keys were merged from an extended
+ * context's, 0 if they were sorted in full. */
+size_t boost_extend_workspace_bytes(const boost_ctx *c, int64_t m);
+int boost_extend(boost_ctx **out, const boost_ctx *c, const uint8_t *d_images, const uint8_t *d_labels,
+                 int64_t m, void *d_workspace, size_t workspace_bytes);
+int boost_extend_merged(const boost_ctx *c);
+
 /* One boosting round (Section 2.3 steps 1-4; Section 3.3.2 master steps 1-4):
  * the normalised weights' best stump over all features and thresholds, its
  * beta and alpha, and the weight update w_i <- w_i beta^(1 - e_i) followed by

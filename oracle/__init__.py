@@ -29,23 +29,32 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvj_oracle.so")
+PLAIN_LIB_PATH = os.path.join(_HERE, "libvj_oracle.so")
+SAN_LIB_PATH = os.path.join(_HERE, "libvj_oracle_san.so")
+# VJB_ORACLE_SAN=1 loads the AddressSanitizer / UndefinedBehaviorSanitizer
+# build (gcc's runtimes must then be preloaded into the interpreter)
+SANITIZED = os.environ.get("VJB_ORACLE_SAN") == "1"
+LIB_PATH = SAN_LIB_PATH if SANITIZED else PLAIN_LIB_PATH
 SRC_PATH = os.path.join(_HERE, "vj_oracle.c")
 
 TYPE_NAMES = ("3h", "3v", "2h", "2v", "4")
 ALL_TYPES = 0x1F
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
-    if force or not os.path.exists(LIB_PATH) or \
-            os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
-        tmp = LIB_PATH + ".tmp"
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math); sanitize:
+    the AddressSanitizer + UndefinedBehaviorSanitizer build instead."""
+    path = SAN_LIB_PATH if sanitize else PLAIN_LIB_PATH
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC_PATH):
+        tmp = path + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
                "-fno-fast-math", "-ffp-contract=off", SRC_PATH, "-o", tmp, "-lm"]
+        if sanitize:
+            cmd[1:1] = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                        "-g"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+        os.replace(tmp, path)
+    return path
 
 
 class _Stump(ctypes.Structure):
@@ -75,7 +84,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build(force=False)
+        build(force=False, sanitize=SANITIZED)
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
         i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double

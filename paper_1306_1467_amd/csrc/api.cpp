@@ -30,7 +30,7 @@ bool valid_options(const boost_options* o) {
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t keys, ii, ftab, w, wtmp, wpart, st, ring, perm, inv, wgbest, cls, pad, scratch, total;
+    size_t keys, ii, ftab, sorder, w, wtmp, wpart, st, ring, perm, inv, wgbest, cls, pad, scratch, total;
 };
 
 static bool make_layout(int64_t n, const boost_feature_set* fs, Layout& L) {
@@ -43,6 +43,7 @@ static bool make_layout(int64_t n, const boost_feature_set* fs, Layout& L) {
     L.keys = take((size_t)F * (size_t)g.row_units * 16);
     L.ii = take((size_t)P * (size_t)ii_stride_of(n) * 4);
     L.ftab = take((size_t)F * 4);
+    L.sorder = take((size_t)F * 4);
     L.w = take((size_t)n * 16);
     L.wtmp = take((size_t)n * 8);
     L.wpart = take((size_t)kMaxPart * 8);
@@ -86,7 +87,7 @@ static int sync_state(hipStream_t s, const JobState* d_st, JobState& st) {
 // preparation: ingest, integral images, per-feature evaluate + sort + keys,
 // initial weights.  Synchronises (label validation needs the count).
 int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, const boost_options* o,
-              const uint8_t* d_images, const uint8_t* d_labels, int num_cu, hipStream_t s) {
+              const uint8_t* d_images, const uint8_t* d_labels, int num_cu, hipStream_t s, const ExtendSrc* ext) {
     Layout L;
     make_layout(n, fs, L);
     JobDev& jd = h.jd;
@@ -113,17 +114,28 @@ int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, cons
     jd.unused = 0;
     jd.eps_floor = o->eps_floor;
     h.wtmp = (double*)(ws + L.wtmp);
+    h.merged = false;
     h.cls = (StumpDev*)(ws + L.cls);
     h.scratch = sort_scratch_bytes(n) ? (uint64_t*)(ws + L.scratch) : nullptr;
 
-    std::vector<uint32_t> ftab((size_t)jd.F);
+    h.sorder = (const uint32_t*)(ws + L.sorder);
+    std::vector<uint32_t> ftab((size_t)jd.F), sorder((size_t)jd.F);
     host_feature_table(fs, ftab.data());
+    host_sort_order(ftab.data(), jd.F, sorder.data());
     const uint32_t pd = pad_dword(jd.g);
     const uint32_t pad_unit[4] = {pd, pd, pd, pd};
     VJB_HIP(hipMemcpyAsync((void*)jd.ftab, ftab.data(), ftab.size() * 4, hipMemcpyHostToDevice, s));
+    VJB_HIP(hipMemcpyAsync((void*)h.sorder, sorder.data(), sorder.size() * 4, hipMemcpyHostToDevice, s));
     VJB_HIP(hipMemcpyAsync((void*)jd.pad, pad_unit, 16, hipMemcpyHostToDevice, s));
     VJB_HIP(hipMemsetAsync(jd.st, 0, sizeof(JobState), s));
     int rc;
+    if (ext != nullptr) {
+        // the union's labels (old windows first) go through the same ingest;
+        // the weight scratch holds them until then
+        uint8_t* ul = (uint8_t*)h.wtmp;
+        if ((rc = union_labels_launch(*ext->old, ext->l0, d_labels, n - ext->old->g.n, ul, s)) != BOOST_OK) return rc;
+        d_labels = ul;
+    }
     if ((rc = ingest_launch(jd, d_labels, n, s)) != BOOST_OK) return rc;
     JobState st;
     if ((rc = sync_state(s, jd.st, st)) != BOOST_OK) return rc;   // also retires the host copies above
@@ -133,8 +145,18 @@ int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, cons
         return BOOST_E_INVALID;
     }
     h.n_pos = st.n_pos;
-    if ((rc = integral_launch(jd, d_images, s)) != BOOST_OK) return rc;
-    if ((rc = sort_launch(jd, h.scratch, num_cu, s)) != BOOST_OK) return rc;
+    if (ext == nullptr) {
+        if ((rc = integral_launch(jd, d_images, s)) != BOOST_OK) return rc;
+        if ((rc = sort_launch(jd, h.sorder, h.scratch, num_cu, s)) != BOOST_OK) return rc;
+    } else {
+        const JobDev& old = *ext->old;
+        if ((rc = extend_ii_launch(jd, old, d_images, s)) != BOOST_OK) return rc;
+        const int64_t lm = st.n_pos - ext->l0;
+        h.merged = n <= kMergeMaxN && old.g.narrow && old.g.lanes == jd.g.lanes;
+        if (h.merged) rc = merge_launch(jd, h.sorder, old.keys, old.g, (int)ext->l0, (int)lm, num_cu, s);
+        else rc = sort_launch(jd, h.sorder, h.scratch, num_cu, s);
+        if (rc != BOOST_OK) return rc;
+    }
     if ((rc = init_weights_launch(jd, s)) != BOOST_OK) return rc;
     return BOOST_OK;
 }
@@ -153,6 +175,7 @@ struct boost_ctx {
     boost_options opts;
     boost_feature_set fs;
     int64_t n = 0, F = 0, n_pos = 0;
+    bool merged = false;   // keys merged from an extended job's (boost_extend)
     ScanPlan plan;
     int schedule = 0;
     std::vector<double> tune_ms;
@@ -217,10 +240,11 @@ size_t boost_workspace_bytes(int64_t n, const boost_feature_set* fs, const boost
 
 static int sync_and_state(boost_ctx* c, JobState& st) { return sync_state(c->stream, c->jd.st, st); }
 
-int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels, int64_t n,
-               const boost_feature_set* fs, const boost_options* o, void* d_workspace, size_t workspace_bytes) {
-    if (!out || !d_images || !d_labels || !d_workspace) { set_error("NULL pointer argument"); return BOOST_E_INVALID; }
-    *out = nullptr;
+// Shared by boost_init and boost_extend: a context over n windows of
+// d_images / d_labels, or (ext) over the union of an old job and them.
+static int init_context(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels, int64_t n,
+                        const boost_feature_set* fs, const boost_options* o, void* d_workspace,
+                        size_t workspace_bytes, const ExtendSrc* ext) {
     int rc = check_job_args(n, fs, o);
     if (rc != BOOST_OK) return rc;
     const size_t need = job_bytes(n, fs);
@@ -247,10 +271,12 @@ int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels
         return fail(BOOST_E_DEVICE);
     }
     JobHost h;
-    if ((rc = setup_job(h, (char*)d_workspace, n, fs, o, d_images, d_labels, c->num_cu, c->stream)) != BOOST_OK)
+    if ((rc = setup_job(h, (char*)d_workspace, n, fs, o, d_images, d_labels, c->num_cu, c->stream, ext)) !=
+        BOOST_OK)
         return fail(rc);
     c->jd = h.jd;
     c->n_pos = h.n_pos;
+    c->merged = h.merged;
     c->wtmp = h.wtmp;
     c->cls = h.cls;
     c->scratch = h.scratch;
@@ -265,6 +291,33 @@ int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels
     if (hipStreamSynchronize(c->stream) != hipSuccess) { set_error("device error during init"); return fail(BOOST_E_DEVICE); }
     *out = c;
     return BOOST_OK;
+}
+
+int boost_init(boost_ctx** out, const uint8_t* d_images, const uint8_t* d_labels, int64_t n,
+               const boost_feature_set* fs, const boost_options* o, void* d_workspace, size_t workspace_bytes) {
+    if (!out || !d_images || !d_labels || !d_workspace) { set_error("NULL pointer argument"); return BOOST_E_INVALID; }
+    *out = nullptr;
+    return init_context(out, d_images, d_labels, n, fs, o, d_workspace, workspace_bytes, nullptr);
+}
+
+size_t boost_extend_workspace_bytes(const boost_ctx* c, int64_t m) {
+    if (!c || m < 1) return 0;
+    return boost_workspace_bytes(c->n + m, &c->fs, &c->opts);
+}
+
+int boost_extend(boost_ctx** out, const boost_ctx* c, const uint8_t* d_images, const uint8_t* d_labels, int64_t m,
+                 void* d_workspace, size_t workspace_bytes) {
+    if (!out || !c || !d_images || !d_labels || !d_workspace) { set_error("NULL pointer argument"); return BOOST_E_INVALID; }
+    *out = nullptr;
+    if (m < 1 || c->n + m > kMaxN) { set_error("m must be >= 1 with n + m <= 32767"); return BOOST_E_INVALID; }
+    if (c->stream) VJB_HIP(hipStreamSynchronize(c->stream));   // the old job's preparation is complete
+    const ExtendSrc ext{&c->jd, c->n_pos};
+    return init_context(out, d_images, d_labels, c->n + m, &c->fs, &c->opts, d_workspace, workspace_bytes, &ext);
+}
+
+int boost_extend_merged(const boost_ctx* c) {
+    if (!c) { set_error("NULL context"); return BOOST_E_INVALID; }
+    return c->merged ? 1 : 0;
 }
 
 static int launch_round(boost_ctx* c, double* d_feature_err, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {

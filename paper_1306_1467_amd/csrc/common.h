@@ -61,6 +61,32 @@ __device__ __forceinline__ int32_t haar_value(const int32_t* __restrict__ ii, in
     }
 }
 
+// The same value with the type known at compile time: a caller that
+// evaluates many windows of one feature dispatches on the type once, so the
+// loads of all its windows can be in flight together.
+template <int TYPE>
+__device__ __forceinline__ int32_t haar_value_t(const int32_t* __restrict__ ii, int64_t S, int wp1, int x, int y,
+                                                int cw, int ch, int64_t i) {
+    auto g = [&](int r, int c) -> int32_t { return ii[(int64_t)(r * wp1 + c) * S + i]; };
+    if constexpr (TYPE == BOOST_TYPE_3H) {
+        auto A = [&](int c) { return g(y + ch, c) - g(y, c); };
+        return 2 * A(x + 2 * cw) - 2 * A(x + cw) + A(x) - A(x + 3 * cw);
+    } else if constexpr (TYPE == BOOST_TYPE_3V) {
+        auto B = [&](int r) { return g(r, x + cw) - g(r, x); };
+        return 2 * B(y + 2 * ch) - 2 * B(y + ch) + B(y) - B(y + 3 * ch);
+    } else if constexpr (TYPE == BOOST_TYPE_2H) {
+        auto A = [&](int c) { return g(y + ch, c) - g(y, c); };
+        return A(x + 2 * cw) - 2 * A(x + cw) + A(x);
+    } else if constexpr (TYPE == BOOST_TYPE_2V) {
+        auto B = [&](int r) { return g(r, x + cw) - g(r, x); };
+        return B(y + 2 * ch) - 2 * B(y + ch) + B(y);
+    } else {
+        const int x1 = x + cw, x2 = x + 2 * cw, y1 = y + ch, y2 = y + 2 * ch;
+        return -g(y, x) + 2 * g(y, x1) - g(y, x2) + 2 * g(y1, x) - 4 * g(y1, x1) + 2 * g(y1, x2) -
+               g(y2, x) + 2 * g(y2, x1) - g(y2, x2);
+    }
+}
+
 // ---------------------------------------------------------------- sorted-key layout
 // Per feature, the n windows in ascending value order are split into 8-key
 // units (16 bytes).  The Nc = ceil(n/8) units are dealt to the `lanes` lanes
@@ -189,6 +215,9 @@ bool valid_feature_set(const boost_feature_set* fs);
 bool valid_options(const boost_options* o);
 int host_feature_desc(const boost_feature_set* fs, int64_t j, boost_feature* out);
 void host_feature_table(const boost_feature_set* fs, uint32_t* out);
+// A permutation of 0 .. F - 1: the order the one-time preparation visits
+// the features of ftab (integral-image locality; see features.cpp).
+void host_sort_order(const uint32_t* ftab, int64_t F, uint32_t* order);
 
 KeyGeom make_geom(int64_t n, int lanes);
 int64_t ii_stride_of(int64_t n);

@@ -4,6 +4,9 @@
 // per-type counts and Section 3.3.2 assigns feature groups).  Base cell grid
 // (columns x rows): 3x1, 1x3, 2x1, 1x2, 2x2.  Cells are cw x ch pixels, scaled
 // independently; index order type, cw, ch, y, x (x fastest).
+#include <algorithm>
+#include <vector>
+
 #include "common.h"
 
 namespace vjb {
@@ -69,6 +72,46 @@ void host_feature_table(const boost_feature_set* fs, uint32_t* out) {
                 for (int y = 0; y + bh * ch <= H; ++y)
                     for (int x = 0; x + bw * cw <= W; ++x) out[j++] = pack_feature(t, x, y, cw, ch);
     }
+}
+
+// Order in which the one-time preparation visits the features (each XCD
+// runs a contiguous share of it).  Features whose corners lie on the same
+// integral-image rows (types one cell high, and the 2x2 type: same y and
+// cell height) or columns (types one cell wide: same x and cell width) are
+// adjacent, so one XCD's L2 holds the corner planes a run of features reads
+// (50 to 75 planes of n words for 24x24 windows).  The groups of the types
+// are interleaved in proportion to the types' sizes, so every XCD's share
+// has the same mix of feature types.
+void host_sort_order(const uint32_t* ftab, int64_t F, uint32_t* order) {
+    // group id: type, then (x, cw) or (y, ch) in 5 + 5 bits (cell sizes 1..32)
+    constexpr int kKeys = 1 << 10;
+    std::vector<int64_t> count(5 * kKeys, 0);
+    std::vector<uint32_t> gid((size_t)F);
+    int64_t type_total[5] = {0, 0, 0, 0, 0};
+    for (int64_t j = 0; j < F; ++j) {
+        int t, x, y, cw, ch;
+        unpack_feature(ftab[j], t, x, y, cw, ch);
+        const uint32_t key = kBaseW[t] == 1 ? (uint32_t)(x << 5 | (cw - 1)) : (uint32_t)(y << 5 | (ch - 1));
+        gid[(size_t)j] = (uint32_t)(t * kKeys) + key;
+        ++count[gid[(size_t)j]];
+        ++type_total[t];
+    }
+    struct Group { double pos; uint32_t id; };
+    std::vector<Group> groups;
+    for (int t = 0; t < 5; ++t) {
+        int64_t before = 0;
+        for (int k = 0; k < kKeys; ++k) {
+            const int64_t sz = count[(size_t)(t * kKeys + k)];
+            if (sz == 0) continue;
+            groups.push_back(Group{((double)before + 0.5 * (double)sz) / (double)type_total[t], (uint32_t)(t * kKeys + k)});
+            before += sz;
+        }
+    }
+    std::stable_sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) { return a.pos < b.pos; });
+    std::vector<int64_t> at(5 * kKeys, 0);
+    int64_t p = 0;
+    for (const Group& g : groups) { at[g.id] = p; p += count[g.id]; }
+    for (int64_t j = 0; j < F; ++j) order[at[gid[(size_t)j]]++] = (uint32_t)j;
 }
 
 KeyGeom make_geom(int64_t n, int lanes) {

@@ -14,7 +14,6 @@
 #include <math.h>
 
 #include <string>
-#include <vector>
 
 #include "launch.h"
 
@@ -92,9 +91,9 @@ int classify_any_launch(const int32_t* ii, int64_t S, int W, int64_t n, const St
     return BOOST_OK;
 }
 
-// Checks stump records against a window and packs them for the device:
-// polarity +-1, finite alpha, a known type whose cells fit the window.
-int pack_stumps(const boost_stump* stumps, int T, int W, int H, StumpDev* out) {
+// Checks stump records against a window: polarity +-1, finite alpha, a
+// known type whose cells fit the window.
+static int check_stumps(const boost_stump* stumps, int T, int W, int H) {
     static const int kBw[5] = {3, 1, 2, 1, 2};
     static const int kBh[5] = {1, 3, 1, 2, 2};
     for (int t = 0; t < T; ++t) {
@@ -108,22 +107,33 @@ int pack_stumps(const boost_stump* stumps, int T, int W, int H, StumpDev* out) {
                       std::to_string(H) + " window");
             return BOOST_E_INVALID;
         }
-        out[t].desc = pack_feature(r.type, r.x, r.y, r.cell_w, r.cell_h);
-        out[t].polarity = r.polarity;
-        out[t].theta = r.threshold;
-        out[t].pad = 0;
-        out[t].alpha = r.alpha;
     }
     return BOOST_OK;
 }
 
-// Layout of the caller's workspace: integral images, then the stump table.
+// The device stump table from records already checked on the host.
+__global__ void k_pack_stumps(const boost_stump* __restrict__ rec, int T, StumpDev* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const boost_stump r = rec[t];
+    StumpDev d;
+    d.desc = pack_feature(r.type, r.x, r.y, r.cell_w, r.cell_h);
+    d.polarity = r.polarity;
+    d.theta = r.threshold;
+    d.pad = 0;
+    d.alpha = r.alpha;
+    out[t] = d;
+}
+
+// Device memory of one call: the windows' integral images, the caller's
+// records as copied, and the packed stump table.
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 static size_t classify_ii_bytes(int64_t n, int W, int H) {
     return a256((size_t)(W + 1) * (size_t)(H + 1) * (size_t)ii_stride_of(n) * 4);
 }
+static size_t classify_rec_bytes() { return a256((size_t)kMaxClassifyT * sizeof(boost_stump)); }
 static size_t classify_bytes(int64_t n, int W, int H) {
-    return classify_ii_bytes(n, W, H) + a256((size_t)kMaxClassifyT * sizeof(StumpDev));
+    return classify_ii_bytes(n, W, H) + classify_rec_bytes() + a256((size_t)kMaxClassifyT * sizeof(StumpDev));
 }
 
 static int check_classify_args(const uint8_t* d_images, int64_t n, int32_t W, int32_t H, const boost_stump* stumps,
@@ -144,19 +154,26 @@ static int check_classify_args(const uint8_t* d_images, int64_t n, int32_t W, in
 }
 
 // Integral images of the windows, the stump table, then the classifier, on
-// stream s, with ii / tab in device memory the caller or the library owns.
+// stream s, in device memory `mem` (classify_bytes(n, W, H) bytes) that the
+// caller or the library owns.  Allocates nothing.  Synchronises.
 static int classify_windows(const uint8_t* d_images, int64_t n, int32_t W, int32_t H, const uint8_t* d_labels,
                             const boost_stump* stumps, int32_t T, uint8_t* d_out, double* d_score,
-                            int32_t* d_err_curve, hipStream_t s, int32_t* ii, StumpDev* tab) {
-    std::vector<StumpDev> h((size_t)(T > 0 ? T : 1));
-    int rc = pack_stumps(stumps, T, W, H, h.data());
+                            int32_t* d_err_curve, hipStream_t s, char* mem) {
+    int rc = check_stumps(stumps, T, W, H);
     if (rc != BOOST_OK) return rc;
+    int32_t* ii = (int32_t*)mem;
+    boost_stump* rec = (boost_stump*)(mem + classify_ii_bytes(n, W, H));
+    StumpDev* tab = (StumpDev*)(mem + classify_ii_bytes(n, W, H) + classify_rec_bytes());
     const int64_t S = ii_stride_of(n);
     if ((rc = integral_raw_launch(d_images, nullptr, n, W, H, ii, S, s)) != BOOST_OK) return rc;
-    if (T > 0) VJB_HIP(hipMemcpyAsync(tab, h.data(), (size_t)T * sizeof(StumpDev), hipMemcpyHostToDevice, s));
+    if (T > 0) {
+        VJB_HIP(hipMemcpyAsync(rec, stumps, (size_t)T * sizeof(boost_stump), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_pack_stumps, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, rec, T, tab);
+        VJB_HIP(hipGetLastError());
+    }
     rc = classify_any_launch(ii, S, W, n, tab, T, nullptr, d_labels, -1, d_out, d_score, d_err_curve, s);
     if (rc != BOOST_OK) return rc;
-    VJB_HIP(hipStreamSynchronize(s));   // the host table h is read by the copy
+    VJB_HIP(hipStreamSynchronize(s));   // the caller's host records are read by the copy
     return BOOST_OK;
 }
 
@@ -182,9 +199,8 @@ int boost_classify(const uint8_t* d_images, int64_t n, int32_t window_w, int32_t
         set_error("classify: workspace too small: need " + std::to_string(need) + " bytes");
         return BOOST_E_NOMEM;
     }
-    char* ws = (char*)d_workspace;
     return classify_windows(d_images, n, window_w, window_h, d_labels, stumps, T, d_out, d_score, d_err_curve,
-                            (hipStream_t)stream, (int32_t*)ws, (StumpDev*)(ws + classify_ii_bytes(n, window_w, window_h)));
+                            (hipStream_t)stream, (char*)d_workspace);
 }
 
 }  // extern "C"

@@ -112,6 +112,63 @@ int integral_launch(const JobDev& jd, const uint8_t* d_images, hipStream_t s) {
     return integral_raw_launch(d_images, jd.perm, jd.g.n, jd.W, jd.H, (int32_t*)jd.ii, jd.ii_stride, s);
 }
 
+// ---------------------------------------------------------------- extending a job
+// Labels of a job extended by m windows, in the union's caller order: the
+// old windows' labels from the old positives-first order (caller window e is
+// positive iff its internal index is below l0), then the new ones.
+__global__ void k_union_labels(const int32_t* __restrict__ old_inv, int64_t n0, int64_t l0,
+                               const uint8_t* __restrict__ new_labels, int64_t m, uint8_t* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n0) out[e] = old_inv[e] < l0 ? 1 : 0;
+    else if (e < n0 + m) out[e] = new_labels[e - n0];
+}
+
+// Integral images of the union: sample i is caller window e = perm[i]; an old
+// window's column entries are copied from its old sample, a new window's
+// image is integrated.
+__global__ void k_extend_ii(const int32_t* __restrict__ perm, int64_t n, int64_t n0,
+                            const int32_t* __restrict__ old_inv, const int32_t* __restrict__ old_ii, int64_t old_S,
+                            const uint8_t* __restrict__ new_images, int W, int H, int32_t* __restrict__ ii, int64_t S) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t e = perm[i];
+    const int wp1 = W + 1;
+    const int64_t P = (int64_t)wp1 * (H + 1);
+    if (e < n0) {
+        const int64_t io = old_inv[e];
+        for (int64_t p = 0; p < P; ++p) ii[p * S + i] = old_ii[p * old_S + io];
+        return;
+    }
+    const uint8_t* img = new_images + (e - n0) * W * H;
+    for (int c = 0; c <= W; ++c) ii[(int64_t)c * S + i] = 0;
+    for (int r = 0; r < H; ++r) {
+        int32_t row = 0;
+        ii[(int64_t)((r + 1) * wp1) * S + i] = 0;
+        for (int c = 0; c < W; ++c) {
+            row += img[r * W + c];
+            const int32_t above = ii[(int64_t)(r * wp1 + c + 1) * S + i];
+            ii[(int64_t)((r + 1) * wp1 + c + 1) * S + i] = above + row;
+        }
+    }
+}
+
+int union_labels_launch(const JobDev& old, int64_t l0, const uint8_t* d_new_labels, int64_t m, uint8_t* d_out,
+                        hipStream_t s) {
+    const int64_t N = old.g.n + m;
+    hipLaunchKernelGGL(k_union_labels, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, old.inv, old.g.n, l0,
+                       d_new_labels, m, d_out);
+    VJB_HIP(hipGetLastError());
+    return BOOST_OK;
+}
+
+int extend_ii_launch(const JobDev& jd, const JobDev& old, const uint8_t* d_new_images, hipStream_t s) {
+    const int64_t n = jd.g.n;
+    hipLaunchKernelGGL(k_extend_ii, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, jd.perm, n, old.g.n, old.inv,
+                       old.ii, old.ii_stride, d_new_images, jd.W, jd.H, (int32_t*)jd.ii, jd.ii_stride);
+    VJB_HIP(hipGetLastError());
+    return BOOST_OK;
+}
+
 // ---------------------------------------------------------------- weights
 // Table 2 of Section 2.3: 1/(2l) for positives, 1/(2m) for negatives.  The
 // stored weights divided by the sum of the partials are the normalised ones

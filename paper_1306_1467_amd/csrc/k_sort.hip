@@ -81,6 +81,59 @@ __device__ void emit_keys(const JobDev& jd, int64_t j, const T* s, int shift, ui
     }
 }
 
+// The keys of units mu = threadIdx.x + k NT (k < U) of a feature's row, from
+// its sorted 32-bit words in LDS (s 16-byte aligned, at least 8 ceil(n / 8)
+// words; a unit's 8 words are read as two 16-byte loads), kept in registers
+// so that the caller chooses when the stores issue.  Entries for units past
+// the row are left unset.
+template <int NT, int U>
+__device__ __forceinline__ void unit_keys_w32(const KeyGeom& g, const uint32_t* s, int shift, uint32_t imask,
+                                              uint4* out, int mu0 = 0) {
+    const int n = (int)g.n;
+    const int nc = (int)g.nc;
+    const int lsh = __builtin_ctz((unsigned)g.lanes);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const int mu = mu0 + threadIdx.x + k * NT;
+        if (mu >= nc) break;
+        const int L = mu & (g.lanes - 1);
+        const int u = L * g.q + (L < g.rem ? L : g.rem) + (mu >> lsh);
+        const uint4 a = *reinterpret_cast<const uint4*>(s + 8 * u);
+        const uint4 b = *reinterpret_cast<const uint4*>(s + 8 * u + 4);
+        const int rn = 8 * u + 8;
+        const uint32_t w[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, s[rn < n ? rn : n - 1]};
+        uint32_t dw[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            uint32_t ix[2], fl[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int q = 2 * h + e, r = 8 * u + q;
+                if (r < n) {
+                    ix[e] = w[q] & imask;
+                    fl[e] = (r == n - 1) || ((w[q] >> shift) != (w[q + 1] >> shift));
+                } else {
+                    ix[e] = (uint32_t)n;   // padding key: zero-weight table slot, no split
+                    fl[e] = 0;
+                }
+            }
+            dw[h] = encode_pair(g.narrow, ix[0], fl[0], ix[1], fl[1]);
+        }
+        out[k] = make_uint4(dw[0], dw[1], dw[2], dw[3]);
+    }
+}
+
+template <int NT, int U>
+__device__ __forceinline__ void store_unit_keys(const JobDev& jd, int64_t j, const uint4* out, int mu0 = 0) {
+    uint4* row = (uint4*)(jd.keys + j * jd.g.row_units);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const int mu = mu0 + threadIdx.x + k * NT;
+        if (mu >= (int)jd.g.nc) break;
+        row[mu] = out[k];
+    }
+}
+
 constexpr int kRadixBits = 4;
 constexpr int kDigits = 1 << kRadixBits;
 
@@ -236,88 +289,222 @@ __global__ __launch_bounds__(NT) void k_sort(JobDev jd, int64_t npow2, int ib, u
 // Unlike ranking each item among its wave with ballots (several VALU
 // operations per key bit), this costs a few operations per item and pass.
 
-// Inclusive / exclusive scan across the 64 lanes of a wave of four 16-bit
-// counters packed in a 64-bit word (no carries cross fields: every sum stays
-// below 2^16).
-template <int CTRL, int RM, int BM, bool BC>
-__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, RM, BM, BC);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, RM, BM, BC);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+// Inclusive scan of a 32-bit value across the 64 lanes of a wave (DPP row
+// shifts and broadcasts; lanes a shift or broadcast does not reach add 0).
+// Also scans two 16-bit counters packed in a word, as long as no field's
+// sum reaches 2^16.
+template <int CTRL, int RM, bool BC>
+__device__ __forceinline__ uint32_t dpp_add(uint32_t v) {
+    return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, RM, 0xF, BC);
 }
-__device__ __forceinline__ uint64_t wave_scan_incl_u64(uint64_t v) {
-    v += dpp64<0x111, 0xF, 0xF, true>(v);   // row_shr:1
-    v += dpp64<0x112, 0xF, 0xF, true>(v);   // row_shr:2
-    v += dpp64<0x114, 0xF, 0xF, true>(v);   // row_shr:4
-    v += dpp64<0x118, 0xF, 0xF, true>(v);   // row_shr:8
-    v += dpp64<0x142, 0xA, 0xF, false>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp64<0x143, 0xC, 0xF, false>(v);  // row_bcast:31 into rows 2 and 3
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
+    v = dpp_add<0x111, 0xF, true>(v);    // row_shr:1
+    v = dpp_add<0x112, 0xF, true>(v);    // row_shr:2
+    v = dpp_add<0x114, 0xF, true>(v);    // row_shr:4
+    v = dpp_add<0x118, 0xF, true>(v);    // row_shr:8
+    v = dpp_add<0x142, 0xA, false>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xC, false>(v);   // row_bcast:31 into rows 2 and 3
     return v;
 }
 
-// Four 4-bit counters (bits 0..15 of x) spread to 16-bit fields.
-__device__ __forceinline__ uint64_t spread4(uint32_t x) {
-    return (uint64_t)(x & 0xFu) | ((uint64_t)((x >> 4) & 0xFu) << 16) | ((uint64_t)((x >> 8) & 0xFu) << 32) |
-           ((uint64_t)((x >> 12) & 0xFu) << 48);
+// Maximum and minimum of a 32-bit signed value over the 64 lanes of a wave
+// (DPP row shifts and broadcasts; a lane a shift or broadcast does not reach
+// keeps its own value), returned uniform from the last lane.
+template <int CTRL, int RM, bool MAX>
+__device__ __forceinline__ int32_t dpp_ext(int32_t v) {
+    const int32_t o = __builtin_amdgcn_update_dpp(v, v, CTRL, RM, 0xF, false);
+    return MAX ? (o > v ? o : v) : (o < v ? o : v);
+}
+template <bool MAX>
+__device__ __forceinline__ int32_t wave_ext(int32_t v) {
+    v = dpp_ext<0x111, 0xF, MAX>(v);   // row_shr:1
+    v = dpp_ext<0x112, 0xF, MAX>(v);   // row_shr:2
+    v = dpp_ext<0x114, 0xF, MAX>(v);   // row_shr:4
+    v = dpp_ext<0x118, 0xF, MAX>(v);   // row_shr:8
+    v = dpp_ext<0x142, 0xA, MAX>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_ext<0x143, 0xC, MAX>(v);   // row_bcast:31 into rows 2 and 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Values of windows k NT + threadIdx.x, k < C (0 past n), the feature type
+// fixed at compile time so the loads of all slots issue together.
+template <int TYPE, int NT, int C>
+__device__ __forceinline__ void eval_windows(const int32_t* __restrict__ ii, int64_t S, int wp1, int x, int y, int cw,
+                                             int ch, int n, int32_t* v) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int i = k * NT + threadIdx.x;
+        v[k] = i < n ? haar_value_t<TYPE>(ii, S, wp1, x, y, cw, ch, i) : 0;
+    }
+}
+
+// Scratch of the counting-sort passes besides the order buffer.
+template <int NT>
+struct CntScratch {
+    uint16_t tab[16 * NT];         // tab[d * NT + t]: thread t's start offset of digit d
+    uint32_t wtot[NT / 64][8];     // per wave: the digit totals, digits 2p, 2p + 1 in word p
+    alignas(16) uint16_t base[NT / 64][16];   // per wave: where each digit's run of this wave starts
+};
+
+// Stable LSD counting-sort passes (4-bit digits) over bits [sh0, sh1) of
+// the NT * C words it[] (thread t holds positions t C .. t C + C - 1 of the
+// current order).  Each pass scatters into buf (NT * C words) and reloads;
+// on return it[] and buf hold the sorted order (buf untouched when no pass
+// runs).  The caller must have finished reading buf (a barrier) before the
+// call; the call ends with buf complete (after a barrier).
+template <int NT, int C>
+__device__ __forceinline__ void cnt_sort_passes(uint32_t* it, uint32_t* buf, CntScratch<NT>& cs, int sh0, int sh1) {
+    static_assert(C <= 15 && (C & 1) == 1, "4-bit counters; odd C keeps the chunk reads conflict-free");
+    constexpr int NW = NT / 64;
+    static_assert(16 * NW <= 256, "one wave scans the (digit, wave) totals, four per lane");
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int sh = sh0; sh < sh1; sh += 4) {
+        // 1. counts: 16 4-bit fields
+        uint64_t cnt = 0;
+#pragma unroll
+        for (int k = 0; k < C; ++k) cnt += 1ull << (4 * ((it[k] >> sh) & 15u));
+        // 2. scan across the wave (digits 2p, 2p + 1 in word p), then across (digit, wave)
+        uint32_t ex[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t c2 = (uint32_t)(cnt >> (8 * p));
+            const uint32_t f = (c2 & 0xFu) | ((c2 & 0xF0u) << 12);
+            const uint32_t inc = wave_scan_incl(f);
+            ex[p] = inc - f;
+            if (lane == 63) cs.wtot[wv][p] = inc;
+        }
+        __syncthreads();   // also: every thread has read its chunk of the previous order
+        if (wv == 0) {
+            // (digit, wave) entries x = d * NW + w in digit-major order, four per lane
+            uint32_t e[4], sum = 0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int x = 4 * lane + a;
+                const int d = x / NW, w = x % NW;
+                e[a] = x < 16 * NW ? (cs.wtot[w][d >> 1] >> (16 * (d & 1))) & 0xFFFFu : 0u;
+                sum += e[a];
+            }
+            const uint32_t incl = wave_scan_incl(sum);
+            uint32_t run = incl - sum;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int x = 4 * lane + a;
+                if (x < 16 * NW) cs.base[x % NW][x / NW] = (uint16_t)run;
+                run += e[a];
+            }
+        }
+        __syncthreads();
+        // 3. this thread's start offsets (the wave's bases read at once, as
+        // digit pairs), then the scatter
+        const uint4 b0 = *reinterpret_cast<const uint4*>(&cs.base[wv][0]);
+        const uint4 b1 = *reinterpret_cast<const uint4*>(&cs.base[wv][8]);
+        const uint32_t bp[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+        uint64_t run = 0;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t s2 = bp[p] + ex[p];
+            cs.tab[(2 * p) * NT + tid] = (uint16_t)s2;
+            cs.tab[(2 * p + 1) * NT + tid] = (uint16_t)(s2 >> 16);
+        }
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const uint32_t d = (it[k] >> sh) & 15u;
+            const uint32_t r = (uint32_t)(run >> (4 * d)) & 15u;
+            run += 1ull << (4 * d);
+            buf[cs.tab[d * NT + tid] + r] = it[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < C; ++k) it[k] = buf[tid * C + k];
+    }
+    __syncthreads();
+}
+
+// Values of feature `desc` on windows k NT + threadIdx.x, k < C: the loads
+// are issued here and waited for where the values are first used.
+template <int NT, int C>
+__device__ __forceinline__ void eval_values(const JobDev& jd, uint32_t desc, int n, int32_t* v) {
+    const int wp1 = jd.W + 1;
+    int t, x, y, cw, ch;
+    unpack_feature(desc, t, x, y, cw, ch);
+    switch (t) {
+    case BOOST_TYPE_3H: eval_windows<BOOST_TYPE_3H, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
+    case BOOST_TYPE_3V: eval_windows<BOOST_TYPE_3V, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
+    case BOOST_TYPE_2H: eval_windows<BOOST_TYPE_2H, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
+    case BOOST_TYPE_2V: eval_windows<BOOST_TYPE_2V, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
+    default: eval_windows<BOOST_TYPE_4, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
+    }
+}
+
+// The range of the values over the first n windows (every thread gets the
+// same; one barrier).
+template <int NT, int C>
+__device__ __forceinline__ void value_range(const int32_t* v, int n, int32_t* rmin, int32_t* rmax, int32_t& vmin,
+                                            int32_t& vmax) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    vmin = INT_MAX;
+    vmax = INT_MIN;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int i = k * NT + tid;
+        if (i < n) {
+            vmin = v[k] < vmin ? v[k] : vmin;
+            vmax = v[k] > vmax ? v[k] : vmax;
+        }
+    }
+    vmin = wave_ext<false>(vmin);
+    vmax = wave_ext<true>(vmax);
+    if (lane == 0) { rmin[wv] = vmin; rmax[wv] = vmax; }
+    __syncthreads();
+    vmin = rmin[0];
+    vmax = rmax[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        vmin = rmin[w] < vmin ? rmin[w] : vmin;
+        vmax = rmax[w] > vmax ? rmax[w] : vmax;
+    }
+}
+
+// The positions of the visiting order (a permutation of the features that
+// keeps features reading the same integral-image corner planes adjacent)
+// that this workgroup runs: XCD x = blockIdx.x % 8 (workgroups are dealt to
+// the 8 XCDs in turn) takes the contiguous share [x F / 8, (x + 1) F / 8),
+// its G / 8 workgroups interleaved over it, so the features that run at the
+// same time on one XCD are adjacent in the order and share that XCD's L2.
+struct FeatureWalk { int64_t p, end, step; };
+__device__ __forceinline__ FeatureWalk feature_walk(int64_t F) {
+    const int64_t G = gridDim.x;
+    if (G % 8 != 0) return FeatureWalk{(int64_t)blockIdx.x, F, G};
+    const int64_t x = blockIdx.x & 7;
+    return FeatureWalk{x * F / 8 + (int64_t)(blockIdx.x >> 3), (x + 1) * F / 8, G / 8};
 }
 
 template <int NT, int C>
 struct SortCntLds {
     uint32_t buf[NT * C];          // the current order (packed words)
-    uint16_t tab[16 * NT];         // tab[d * NT + t]: thread t's start offset of digit d
-    uint64_t wtot[NT / 64][4];     // per wave: the digit totals, 16-bit fields
-    uint16_t base[NT / 64][16];    // per wave: where each digit's run of this wave starts
+    CntScratch<NT> cs;
     int32_t rmin[NT / 64], rmax[NT / 64];
 };
 
+// One feature per workgroup at a time, in the visiting order sorder.
 template <int NT, int C>
-__global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, int ib) {
-    static_assert(C <= 15 && (C & 1) == 1, "4-bit counters; odd C keeps the chunk reads conflict-free");
-    constexpr int NW = NT / 64;
-    static_assert(16 * NW <= 256, "one wave scans the (digit, wave) totals, four per lane");
+__global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, const uint32_t* __restrict__ ftab,
+                                                 const uint32_t* __restrict__ sorder, int ib) {
+    constexpr int U = (C + 7) / 8;   // key units per thread: ceil(n / 8) <= U NT
     extern __shared__ __align__(16) unsigned char smem[];
     SortCntLds<NT, C>& L = *reinterpret_cast<SortCntLds<NT, C>*>(smem);
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x;
     const int n = (int)jd.g.n;
-    const int wp1 = jd.W + 1;
-    // consecutive features run at the same time on the same XCD (workgroups
-    // are dealt to the 8 XCDs in turn), so the integral-image columns they
-    // share are read from that XCD's L2
-    const int G = gridDim.x;
-    const int per_xcd = G / 8;
-    const int slot = G % 8 == 0 ? (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3) : blockIdx.x;
-    for (int64_t j = slot; j < jd.F; j += G) {
-        const uint32_t desc = jd.ftab[j];
-        // 1. values, all loads of a thread in flight together
-        int32_t v[C];
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const int i = k * NT + tid;
-            v[k] = i < n ? haar_value(jd.ii, jd.ii_stride, wp1, desc, i) : 0;
-        }
-        int32_t vmin = INT_MAX, vmax = INT_MIN;
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const int i = k * NT + tid;
-            if (i < n) {
-                vmin = v[k] < vmin ? v[k] : vmin;
-                vmax = v[k] > vmax ? v[k] : vmax;
-            }
-        }
-#pragma unroll
-        for (int o = 32; o; o >>= 1) {
-            const int32_t a = __shfl_xor(vmin, o), b = __shfl_xor(vmax, o);
-            vmin = a < vmin ? a : vmin;
-            vmax = b > vmax ? b : vmax;
-        }
-        if (lane == 0) { L.rmin[wv] = vmin; L.rmax[wv] = vmax; }
-        __syncthreads();
-        vmin = L.rmin[0]; vmax = L.rmax[0];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) {
-            vmin = L.rmin[w] < vmin ? L.rmin[w] : vmin;
-            vmax = L.rmax[w] > vmax ? L.rmax[w] : vmax;
-        }
+    for (FeatureWalk wk = feature_walk(jd.F); wk.p < wk.end; wk.p += wk.step) {
+        const int64_t j = sorder[wk.p];
+        int32_t v[C], vmin, vmax;
+#if VJB_EXP_VDESC
+        eval_values<NT, C>(jd, jd.ftab[j], n, v);
+#else
+        eval_values<NT, C>(jd, ftab[j], n, v);
+#endif
+        value_range<NT, C>(v, n, L.rmin, L.rmax, vmin, vmax);
         const uint32_t range = (uint32_t)(vmax - vmin);
         const int rb = range == 0 ? 0 : 32 - __clz(range);   // <= 18 for windows up to 32x32, ib <= 14
         // packed words in index order; positions past n hold all-ones
@@ -331,70 +518,168 @@ __global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, int ib) {
         uint32_t it[C];
 #pragma unroll
         for (int k = 0; k < C; ++k) it[k] = L.buf[tid * C + k];
-        for (int sh = ib; sh < ib + rb; sh += 4) {
-            // 1. counts
-            uint64_t cnt = 0;
+        cnt_sort_passes<NT, C>(it, L.buf, L.cs, ib, ib + rb);
 #pragma unroll
-            for (int k = 0; k < C; ++k) cnt += 1ull << (4 * ((it[k] >> sh) & 15u));
-            // 2. scan across the wave, then across (digit, wave)
-            uint64_t f[4], ex[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                f[q] = spread4((uint32_t)(cnt >> (16 * q)) & 0xFFFFu);
-                const uint64_t inc = wave_scan_incl_u64(f[q]);
-                ex[q] = inc - f[q];
-                if (lane == 63) L.wtot[wv][q] = inc;
-            }
-            __syncthreads();   // also: every thread has read its chunk of the previous order
-            if (wv == 0) {
-                // (digit, wave) entries x = d * NW + w in digit-major order, four per lane
-                uint32_t e[4], sum = 0;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const int x = 4 * lane + a;
-                    const int d = x / NW, w = x % NW;
-                    e[a] = x < 16 * NW ? (uint32_t)((L.wtot[w][d >> 2] >> (16 * (d & 3))) & 0xFFFFu) : 0u;
-                    sum += e[a];
-                }
-                uint32_t incl = sum;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const uint32_t y = __shfl_up(incl, o);
-                    if (lane >= o) incl += y;
-                }
-                uint32_t run = incl - sum;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const int x = 4 * lane + a;
-                    if (x < 16 * NW) L.base[x % NW][x / NW] = (uint16_t)run;
-                    run += e[a];
-                }
-            }
-            __syncthreads();
-            // 3. this thread's start offsets, then the scatter
-#pragma unroll
-            for (int d = 0; d < 16; ++d)
-                L.tab[d * NT + tid] = (uint16_t)(L.base[wv][d] + (uint32_t)((ex[d >> 2] >> (16 * (d & 3))) & 0xFFFFu));
-            uint64_t run = 0;
-#pragma unroll
-            for (int k = 0; k < C; ++k) {
-                const uint32_t d = (it[k] >> sh) & 15u;
-                const uint32_t r = (uint32_t)(run >> (4 * d)) & 15u;
-                run += 1ull << (4 * d);
-                L.buf[L.tab[d * NT + tid] + r] = it[k];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < C; ++k) it[k] = L.buf[tid * C + k];
+        for (int k = 0; k < U; ++k) {
+            uint4 kq;
+            unit_keys_w32<NT, 1>(jd.g, L.buf, ib, (1u << ib) - 1u, &kq, k * NT);
+            store_unit_keys<NT, 1>(jd, j, &kq, k * NT);
         }
-        __syncthreads();
-        emit_keys<NT, uint32_t>(jd, j, L.buf, ib, (1u << ib) - 1u);
         __syncthreads();
     }
 }
 
+// ---------------------------------------------------------------- incremental preparation
+// Keys of a job extended by m new windows (the union's internal order: the
+// old positives, the new positives, the old negatives, the new negatives),
+// from the old job's keys: the old windows' order is already known, so only
+// the new windows are sorted, and the two ordered lists are merged.
+//   1. the union's values of the feature (one per window, as in k_sort_cnt)
+//      and its packed words in index order;
+//   2. the new windows' words, sorted by the counting-sort passes (m <= 1024 CB);
+//   3. the old windows' words in the old order (decoded from the old keys,
+//      each old index moved to its union index; the move keeps their order);
+//   4. a merge of the two lists (merge path: each thread finds where its E
+//      outputs start by a binary search, then merges E words);
+//   5. the keys in the union's layout.
+// The words are unique (they carry the window index), so the result is
+// exactly the (value, index) order a full sort of the union gives.
+struct MergeArgs {
+    const uint4* old_keys;   // the old job's keys
+    KeyGeom og;              // their geometry
+    int32_t l0, lm, n0, m;   // old positives, new positives, old windows, new windows
+    int32_t ib;              // index bits of the union
+    int32_t rb_off, x_off;   // LDS byte offsets of the new words' buffer and of the shared region
+};
+
+template <int CB>
+__global__ __launch_bounds__(1024) void k_merge(JobDev jd, const uint32_t* __restrict__ sorder, MergeArgs ma) {
+    constexpr int NT = 1024, C = 15;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* buf = (uint32_t*)smem;                         // NT * C words: index order, then the merged order
+    uint32_t* rbuf = (uint32_t*)(smem + ma.rb_off);          // NT * CB words: the new windows' order
+    CntScratch<NT>& cs = *(CntScratch<NT>*)(smem + ma.x_off);   // during the passes ...
+    uint32_t* abuf = (uint32_t*)(smem + ma.x_off);           // ... then the old windows' order
+    __shared__ int32_t rmin[NT / 64], rmax[NT / 64];
+    const int tid = threadIdx.x;
+    const int n = (int)jd.g.n;           // n0 + m
+    const int mn = ma.m - ma.lm;         // new negatives: union indices n - mn .. n - 1
+    const int E = (n + NT - 1) / NT;
+    const KeyGeom& og = ma.og;
+    for (FeatureWalk wk = feature_walk(jd.F); wk.p < wk.end; wk.p += wk.step) {
+        const int64_t j = sorder[wk.p];
+        // 1.
+        int32_t v[C], vmin, vmax;
+        eval_values<NT, C>(jd, jd.ftab[j], n, v);
+        value_range<NT, C>(v, n, rmin, rmax, vmin, vmax);
+        const uint32_t range = (uint32_t)(vmax - vmin);
+        const int rb = range == 0 ? 0 : 32 - __clz(range);
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int i = k * NT + tid;
+            if (i < n) buf[i] = (((uint32_t)(v[k] - vmin)) << ma.ib) | (uint32_t)i;
+        }
+        __syncthreads();
+        // 2. the new windows, index order: union indices l0 .. l0 + lm - 1, then n - mn .. n - 1
+        uint32_t it[CB];
+#pragma unroll
+        for (int k = 0; k < CB; ++k) {
+            const int p = tid * CB + k;
+            it[k] = p < ma.m ? buf[p < ma.lm ? ma.l0 + p : n - mn + (p - ma.lm)] : 0xFFFFFFFFu;
+            rbuf[p] = it[k];
+        }
+        __syncthreads();
+        cnt_sort_passes<NT, CB>(it, rbuf, cs, ma.ib, ma.ib + rb);
+        // 3. the old windows in the old order
+        for (int u = tid; u < (int)og.nc; u += NT) {
+            const int L = u < (og.q + 1) * og.rem ? u / (og.q + 1) : og.rem + (u - (og.q + 1) * og.rem) / og.q;
+            const int r = u - (L * og.q + (L < og.rem ? L : og.rem));   // unit within lane L's segment
+            const uint4 q4 = ma.old_keys[j * og.row_units + (int64_t)r * og.lanes + L];
+            const uint32_t dw[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                uint32_t i0, f0, i1, f1;
+                decode_pair(og.narrow, dw[h], i0, f0, i1, f1);
+                const int r0 = 8 * u + 2 * h;
+                if (r0 < ma.n0) abuf[r0] = buf[(int)i0 < ma.l0 ? i0 : i0 + ma.lm];
+                if (r0 + 1 < ma.n0) abuf[r0 + 1] = buf[(int)i1 < ma.l0 ? i1 : i1 + ma.lm];
+            }
+        }
+        __syncthreads();
+        // 4. merge: outputs [p0, p1) of this thread
+        {
+            const int p0 = tid * E < n ? tid * E : n;
+            const int p1 = p0 + E < n ? p0 + E : n;
+            int lo = p0 > ma.m ? p0 - ma.m : 0, hi = p0 < ma.n0 ? p0 : ma.n0;
+            while (lo < hi) {   // the number a of old words among the first p0 outputs
+                const int mid = (lo + hi) >> 1;
+                if (abuf[mid] < rbuf[p0 - 1 - mid]) lo = mid + 1; else hi = mid;
+            }
+            int a = lo, b = p0 - lo;
+            uint32_t wa = a < ma.n0 ? abuf[a] : 0xFFFFFFFFu, wb = b < ma.m ? rbuf[b] : 0xFFFFFFFFu;
+            uint32_t out[C];
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                if (k < E && p0 + k < p1) {
+                    const bool ta = wa < wb;
+                    out[k] = ta ? wa : wb;
+                    if (ta) { ++a; wa = a < ma.n0 ? abuf[a] : 0xFFFFFFFFu; }
+                    else { ++b; wb = b < ma.m ? rbuf[b] : 0xFFFFFFFFu; }
+                }
+            }
+            __syncthreads();   // every thread has read its merge inputs' positions ... (buf is rewritten next)
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+                if (k < E && p0 + k < p1) buf[p0 + k] = out[k];
+        }
+        __syncthreads();
+        // 5.
+        uint4 kq[2];
+        unit_keys_w32<NT, 2>(jd.g, buf, ma.ib, (1u << ma.ib) - 1u, kq);
+        store_unit_keys<NT, 2>(jd, j, kq);
+        __syncthreads();
+    }
+}
+
+int merge_launch(const JobDev& jd, const uint32_t* sorder, const uint4* old_keys, const KeyGeom& og, int l0, int lm, int num_cu,
+                 hipStream_t s) {
+    const int64_t n = jd.g.n;
+    const int n0 = (int)og.n, m = (int)(n - og.n);
+    if (n > 1024 * 15 || m < 1 || !og.narrow) {
+        set_error("merge: the union must fit 15,360 windows and the old keys must be narrow");
+        return BOOST_E_INVALID;
+    }
+    MergeArgs ma;
+    ma.old_keys = old_keys;
+    ma.og = og;
+    ma.l0 = l0; ma.lm = lm; ma.n0 = n0; ma.m = m;
+    ma.ib = n <= 1 ? 1 : 32 - __builtin_clz((unsigned)(n - 1));
+    const int cb = m <= 1024 ? 1 : m <= 3 * 1024 ? 3 : m <= 7 * 1024 ? 7 : 15;
+    auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
+    ma.rb_off = (int)a16((size_t)1024 * 15 * 4);
+    ma.x_off = (int)a16((size_t)ma.rb_off + (size_t)1024 * cb * 4);
+    size_t xbytes = (size_t)n0 * 4 > sizeof(CntScratch<1024>) ? (size_t)n0 * 4 : sizeof(CntScratch<1024>);
+    const size_t lds = (size_t)ma.x_off + a16(xbytes);
+    const void* k = cb == 1 ? (const void*)k_merge<1> : cb == 3 ? (const void*)k_merge<3>
+                  : cb == 7 ? (const void*)k_merge<7> : (const void*)k_merge<15>;
+    VJB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    VJB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 1024, lds));
+    if (per_cu < 1) {
+        set_error("merge kernel does not fit on a compute unit");
+        return BOOST_E_INVALID;
+    }
+    int64_t grid = (int64_t)per_cu * num_cu;
+    if (grid > jd.F) grid = jd.F;
+    if (grid > kMaxSortGrid) grid = kMaxSortGrid;
+    JobDev a = jd;
+    void* args[] = {(void*)&a, (void*)&sorder, (void*)&ma};
+    VJB_HIP(hipLaunchKernel(k, dim3((unsigned)grid), dim3(1024), args, lds, s));
+    return BOOST_OK;
+}
+
 template <int NT, int C>
-static int sort_cnt_launch(const JobDev& jd, int num_cu, hipStream_t s) {
+static int sort_cnt_launch(const JobDev& jd, const uint32_t* sorder, int num_cu, hipStream_t s) {
     const int64_t n = jd.g.n;
     int ib = n <= 1 ? 1 : 32 - __builtin_clz((unsigned)(n - 1));
     const size_t lds = sizeof(SortCntLds<NT, C>);
@@ -410,7 +695,8 @@ static int sort_cnt_launch(const JobDev& jd, int num_cu, hipStream_t s) {
     if (grid > jd.F) grid = jd.F;
     if (grid > kMaxSortGrid) grid = kMaxSortGrid;
     JobDev a = jd;
-    void* args[] = {(void*)&a, (void*)&ib};
+    const uint32_t* ftab = jd.ftab;
+    void* args[] = {(void*)&a, (void*)&ftab, (void*)&sorder, (void*)&ib};
     VJB_HIP(hipLaunchKernel(k, dim3((unsigned)grid), dim3(NT), args, lds, s));
     return BOOST_OK;
 }
@@ -444,13 +730,13 @@ static int sort_launch_c(const JobDev& jd, uint64_t* scratch, int num_cu, hipStr
 
 // Counting-sort passes up to 15,360 windows (C values per thread, the
 // smallest odd C of the shape that covers n); ballot-ranked passes beyond.
-int sort_launch(const JobDev& jd, uint64_t* scratch, int num_cu, hipStream_t s) {
+int sort_launch(const JobDev& jd, const uint32_t* sorder, uint64_t* scratch, int num_cu, hipStream_t s) {
     const int64_t n = jd.g.n;
-    if (n <= 256 * 7) return sort_cnt_launch<256, 7>(jd, num_cu, s);
-    if (n <= 512 * 7) return sort_cnt_launch<512, 7>(jd, num_cu, s);
-    if (n <= 1024 * 7) return sort_cnt_launch<1024, 7>(jd, num_cu, s);
-    if (n <= 1024 * 11) return sort_cnt_launch<1024, 11>(jd, num_cu, s);
-    if (n <= 1024 * 15) return sort_cnt_launch<1024, 15>(jd, num_cu, s);
+    if (n <= 256 * 7) return sort_cnt_launch<256, 7>(jd, sorder, num_cu, s);
+    if (n <= 512 * 7) return sort_cnt_launch<512, 7>(jd, sorder, num_cu, s);
+    if (n <= 1024 * 7) return sort_cnt_launch<1024, 7>(jd, sorder, num_cu, s);
+    if (n <= 1024 * 11) return sort_cnt_launch<1024, 11>(jd, sorder, num_cu, s);
+    if (n <= 1024 * 15) return sort_cnt_launch<1024, 15>(jd, sorder, num_cu, s);
     if (n <= 256) return sort_launch_c<256, 1>(jd, scratch, num_cu, s);
     if (n <= 512) return sort_launch_c<256, 2>(jd, scratch, num_cu, s);
     if (n <= 1024) return sort_launch_c<256, 4>(jd, scratch, num_cu, s);

@@ -25,11 +25,18 @@ struct ScanPlan {
 };
 
 // api.cpp: one job's layout and one-time preparation (shared by the batch)
-struct JobHost { JobDev jd; double* wtmp; StumpDev* cls; uint64_t* scratch; int64_t n_pos; };
+struct JobHost { JobDev jd; double* wtmp; StumpDev* cls; uint64_t* scratch; const uint32_t* sorder; int64_t n_pos; bool merged; };
+// A prepared job that a new job extends: the new job's windows are the old
+// job's (in its caller order) followed by the new ones.
+struct ExtendSrc { const JobDev* old; int64_t l0; };
+constexpr int64_t kMergeMaxN = 1024 * 15;   // unions up to this size merge the old keys; larger ones are sorted
 int check_job_args(int64_t n, const boost_feature_set* fs, const boost_options* o);
 size_t job_bytes(int64_t n, const boost_feature_set* fs);
+// ext == NULL: a job of d_images / d_labels (n windows).  Otherwise the union
+// of ext's job and the n - ext->old->g.n windows of d_images / d_labels.
 int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, const boost_options* o,
-              const uint8_t* d_images, const uint8_t* d_labels, int num_cu, hipStream_t s);
+              const uint8_t* d_images, const uint8_t* d_labels, int num_cu, hipStream_t s,
+              const ExtendSrc* ext = nullptr);
 
 // k_scan.hip
 int scan_schedule_count();
@@ -80,11 +87,18 @@ int integral_raw_launch(const uint8_t* d_images, const int32_t* perm, int64_t n,
 int classify_any_launch(const int32_t* ii, int64_t S, int W, int64_t n, const StumpDev* d_stumps, int T,
                         const int32_t* perm, const uint8_t* labels, int64_t l, uint8_t* d_out, double* d_score,
                         int32_t* d_curve, hipStream_t s);
-int pack_stumps(const boost_stump* stumps, int T, int W, int H, StumpDev* out);
+
+// extending a job by m windows (the union's caller order: old windows, then new)
+int union_labels_launch(const JobDev& old, int64_t l0, const uint8_t* d_new_labels, int64_t m, uint8_t* d_out,
+                        hipStream_t s);
+int extend_ii_launch(const JobDev& jd, const JobDev& old, const uint8_t* d_new_images, hipStream_t s);
+// keys of the union from the old keys (union <= 15,360 windows, old keys narrow)
+int merge_launch(const JobDev& jd, const uint32_t* sorder, const uint4* old_keys, const KeyGeom& og, int l0, int lm, int num_cu,
+                 hipStream_t s);
 
 // k_sort.hip
 int64_t sort_pow2(int64_t n);
 size_t sort_scratch_bytes(int64_t n);
-int sort_launch(const JobDev& jd, uint64_t* scratch, int num_cu, hipStream_t s);
+int sort_launch(const JobDev& jd, const uint32_t* sorder, uint64_t* scratch, int num_cu, hipStream_t s);
 
 }  // namespace vjb

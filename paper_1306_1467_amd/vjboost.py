@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvjboost.so")
+# VJBOOST_LIB selects another build of the library (the sanitizer build)
+LIB_PATH = os.environ.get("VJBOOST_LIB") or os.path.join(HERE, "libvjboost.so")
 
 BOOST_OK = 0
 BOOST_E_INVALID = -1
@@ -88,6 +89,9 @@ _SIGS = {
     "boost_probe_stream": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "boost_init": (ctypes.c_int, [ctypes.POINTER(_P), _P, _P, ctypes.c_int64, ctypes.POINTER(FeatureSet),
                                   ctypes.POINTER(Options), _P, ctypes.c_size_t]),
+    "boost_extend_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int64]),
+    "boost_extend": (ctypes.c_int, [ctypes.POINTER(_P), _P, _P, _P, ctypes.c_int64, _P, ctypes.c_size_t]),
+    "boost_extend_merged": (ctypes.c_int, [_P]),
     "boost_round": (ctypes.c_int, [_P, ctypes.POINTER(Stump), _P]),
     "boost_train": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "boost_get_weights": (ctypes.c_int, [_P, _P]),
@@ -198,6 +202,23 @@ def boost_init(d_images, d_labels, n: int, fs: FeatureSet, opts: Options, d_work
     _check(lib().boost_init(ctypes.byref(h), _ptr(d_images), _ptr(d_labels), n, ctypes.byref(fs),
                             ctypes.byref(opts), _ptr(d_workspace), workspace_bytes))
     return h
+
+
+def boost_extend_workspace_bytes(ctx, m: int) -> int:
+    return int(lib().boost_extend_workspace_bytes(ctx, m))
+
+
+def boost_extend(ctx, d_images, d_labels, m: int, d_workspace, workspace_bytes: int):
+    h = ctypes.c_void_p()
+    _check(lib().boost_extend(ctypes.byref(h), ctx, _ptr(d_images), _ptr(d_labels), m, _ptr(d_workspace),
+                              workspace_bytes))
+    return h
+
+
+def boost_extend_merged(ctx) -> bool:
+    rc = lib().boost_extend_merged(ctx)
+    _check(min(rc, 0))
+    return rc == 1
 
 
 def boost_round(ctx, want_record: bool = True, d_feature_err=None):
@@ -405,6 +426,34 @@ class Trainer:
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         torch.cuda.synchronize(self.device)
         self.ctx = boost_init(self.images, self.labels, self.n, self.fs, self.opts, self.workspace, self.ws_bytes)
+
+    def extend(self, images, labels):
+        """A new Trainer over this trainer's windows followed by `images` /
+        `labels` (boost_extend: the old windows' order is reused)."""
+        torch = _torch()
+        img = torch.as_tensor(images)
+        lab = torch.as_tensor(labels)
+        if img.dtype != torch.uint8 or lab.dtype != torch.uint8 or img.dim() != 3 or \
+                tuple(img.shape[1:]) != (self.h, self.w):
+            raise ValueError("images must be uint8 [M, H, W] of this trainer's window size, labels uint8 [M]")
+        new = Trainer.__new__(Trainer)
+        new.device = self.device
+        m = int(img.shape[0])
+        new.n, new.h, new.w = self.n + m, self.h, self.w
+        new.images = img.to(self.device).contiguous()
+        new.labels = lab.to(self.device).contiguous()
+        new.stream = self.stream
+        new.fs, new.opts, new.F = self.fs, self.opts, self.F
+        new.ws_bytes = boost_extend_workspace_bytes(self.ctx, m)
+        if new.ws_bytes == 0:
+            raise BoostError(BOOST_E_INVALID, last_error())
+        new.workspace = torch.empty(new.ws_bytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        new.ctx = boost_extend(self.ctx, new.images, new.labels, m, new.workspace, new.ws_bytes)
+        return new
+
+    def merged(self) -> bool:
+        return boost_extend_merged(self.ctx)
 
     # every device output is allocated here and filled on the library's stream
     def _sync(self):
