@@ -329,6 +329,26 @@ int boost_classify(const uint8_t *d_images, int64_t n, int32_t window_w, int32_t
                    uint8_t *d_out, double *d_score, int32_t *d_err_curve,
                    void *stream, void *d_workspace, size_t workspace_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * boost_classify with no workspace argument.  The integral images and the
+ * stump table live in a 32 MiB device buffer of the library's own, a
+ * file-scope array that each GPU the library runs on holds from the
+ * library's load until the process ends; the call allocates nothing.
+ * Arguments, results, errors and synchronisation as boost_classify; in
+ * addition BOOST_E_INVALID when the windows do not fit the buffer
+ * (boost_classify_noalloc_max_windows(window_w, window_h) per call: 13,248
+ * windows of 24x24, 7,552 of 32x32; split larger sets).  Every call on a GPU
+ * shares that GPU's buffer, which keeps the last call's contents: calls that
+ * overlap on one GPU (two streams, two host threads) race, so serialise
+ * them.
+ * boost_classify_noalloc_max_windows: the largest n one call accepts for that
+ * window size; 0 for a window outside 1..32. */
+size_t boost_classify_noalloc_max_windows(int32_t window_w, int32_t window_h);
+int boost_classify_noalloc(const uint8_t *d_images, int64_t n, int32_t window_w, int32_t window_h,
+                           const uint8_t *d_labels, const boost_stump *stumps, int32_t T,
+                           uint8_t *d_out, double *d_score, int32_t *d_err_curve, void *stream);
+
 void boost_destroy(boost_ctx *c);
 
 /* ------------------------------------------------------------ batched jobs

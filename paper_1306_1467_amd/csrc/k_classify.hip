@@ -13,6 +13,7 @@
 // then added to the output curve with one atomic per (workgroup, stump).
 #include <math.h>
 
+#include <mutex>
 #include <string>
 
 #include "launch.h"
@@ -177,6 +178,35 @@ static int classify_windows(const uint8_t* d_images, int64_t n, int32_t W, int32
     return BOOST_OK;
 }
 
+// ---------------------------------------------------------------- the allocation-free variant
+// Device memory of boost_classify_noalloc: a file-scope array that every GPU
+// the library runs on holds from module load until the process ends.  Host
+// code never passes `scratch` itself (its host-side name is a stand-in, not a
+// device address): the device address of each GPU's copy is looked up once
+// per device with that device current, and only that address is used.
+constexpr size_t kNoAllocBytes = (size_t)32 << 20;   // 32 MiB
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static int scratch_ptr(int device, char** out) {
+    if (device < 0 || device >= kMaxDevices) { set_error("device index out of range"); return BOOST_E_DEVICE; }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device] == nullptr) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return BOOST_E_DEVICE;
+        }
+        g_scratch_ptr[device] = p;
+    }
+    *out = (char*)g_scratch_ptr[device];
+    return BOOST_OK;
+}
+
 }  // namespace vjb
 
 using namespace vjb;
@@ -201,6 +231,38 @@ int boost_classify(const uint8_t* d_images, int64_t n, int32_t window_w, int32_t
     }
     return classify_windows(d_images, n, window_w, window_h, d_labels, stumps, T, d_out, d_score, d_err_curve,
                             (hipStream_t)stream, (char*)d_workspace);
+}
+
+size_t boost_classify_noalloc_max_windows(int32_t window_w, int32_t window_h) {
+    if (window_w < 1 || window_w > kMaxWindow || window_h < 1 || window_h > kMaxWindow) return 0;
+    // classify_bytes grows with n in steps of 64 windows (the integral images' stride)
+    const size_t fixed = classify_rec_bytes() + a256((size_t)kMaxClassifyT * sizeof(StumpDev));
+    const size_t per64 = (size_t)(window_w + 1) * (size_t)(window_h + 1) * 64 * 4;
+    if (kNoAllocBytes <= fixed + 256) return 0;
+    size_t n = (kNoAllocBytes - fixed - 255) / per64 * 64;
+    while (n > 0 && classify_bytes((int64_t)n, window_w, window_h) > kNoAllocBytes) n -= 64;
+    return n;
+}
+
+int boost_classify_noalloc(const uint8_t* d_images, int64_t n, int32_t window_w, int32_t window_h,
+                           const uint8_t* d_labels, const boost_stump* stumps, int32_t T, uint8_t* d_out,
+                           double* d_score, int32_t* d_err_curve, void* stream) {
+    int rc = check_classify_args(d_images, n, window_w, window_h, stumps, T, d_labels, d_err_curve);
+    if (rc != BOOST_OK) return rc;
+    const size_t need = classify_bytes(n, window_w, window_h);
+    if (need > kNoAllocBytes) {
+        set_error("classify_noalloc: " + std::to_string(n) + " windows of " + std::to_string(window_w) + "x" +
+                  std::to_string(window_h) + " need " + std::to_string(need) + " bytes of its " +
+                  std::to_string(kNoAllocBytes) + "-byte device buffer (at most " +
+                  std::to_string(boost_classify_noalloc_max_windows(window_w, window_h)) + " windows per call)");
+        return BOOST_E_INVALID;
+    }
+    int device = 0;
+    VJB_HIP(hipGetDevice(&device));
+    char* mem = nullptr;
+    if ((rc = scratch_ptr(device, &mem)) != BOOST_OK) return rc;
+    return classify_windows(d_images, n, window_w, window_h, d_labels, stumps, T, d_out, d_score, d_err_curve,
+                            (hipStream_t)stream, mem);
 }
 
 }  // extern "C"

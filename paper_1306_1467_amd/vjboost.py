@@ -107,6 +107,9 @@ _SIGS = {
     "boost_classify_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
     "boost_classify": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32,
                                       _P, _P, _P, _P, _P, ctypes.c_size_t]),
+    "boost_classify_noalloc_max_windows": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "boost_classify_noalloc": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                              ctypes.c_int32, _P, _P, _P, _P]),
     "boost_destroy": (None, [_P]),
     "boost_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, _P, ctypes.POINTER(Options)]),
     "boost_batch_init": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.POINTER(Options), _P,
@@ -312,6 +315,18 @@ def boost_classify(d_images, n: int, window_w: int, window_h: int, d_labels, stu
     _check(lib().boost_classify(_ptr(d_images), n, window_w, window_h, _ptr(d_labels),
                                 stumps.ctypes.data if len(stumps) else None, len(stumps), _ptr(d_out), _ptr(d_score),
                                 _ptr(d_curve), stream, _ptr(d_workspace), workspace_bytes))
+
+
+def boost_classify_noalloc_max_windows(window_w: int, window_h: int) -> int:
+    return int(lib().boost_classify_noalloc_max_windows(window_w, window_h))
+
+
+def boost_classify_noalloc(d_images, n: int, window_w: int, window_h: int, d_labels, stumps: np.ndarray, d_out,
+                           d_score, d_curve, stream):
+    stumps = np.ascontiguousarray(stumps, dtype=STUMP_DTYPE)
+    _check(lib().boost_classify_noalloc(_ptr(d_images), n, window_w, window_h, _ptr(d_labels),
+                                        stumps.ctypes.data if len(stumps) else None, len(stumps), _ptr(d_out),
+                                        _ptr(d_score), _ptr(d_curve), stream))
 
 
 def classify(images, stumps, labels=None, device: str = "cuda:0"):
