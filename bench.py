@@ -365,6 +365,7 @@ def run_batched(name, precision, args, torch, vb, specs, data):
                          schedule_id=args.batch_schedule)
     bt.sync()
     init_s = time.perf_counter() - t0
+    lib_init_s, alloc_s = bt.init_s, bt.alloc_s
     bt.train(1, False)
     bt.sync()
     t0 = time.perf_counter()
@@ -372,6 +373,7 @@ def run_batched(name, precision, args, torch, vb, specs, data):
     t_batch = time.perf_counter() - t0
     same = all(recs[:, k].tobytes() == plain[k].tobytes() for k in range(len(data)))
     chosen = bt.schedule()
+    bt_ws = bt.ws_bytes
     keys = sum(vb.boost_feature_count(vb.feature_set(s.size)) * s.n for s in specs)
     jr = len(data) * rounds
     bt.close()
@@ -386,7 +388,12 @@ def run_batched(name, precision, args, torch, vb, specs, data):
             "speedup_vs_plain": round(t_plain / t_batch, 3),
             "batched_ms_per_round": round(t_batch * 1e3 / rounds, 3),
             "batched_key_GBps": round(keys * 2 * rounds / t_batch / 1e9, 1),
-            "batched_init_s": round(init_s, 2),
+            "batched_init_s": round(lib_init_s, 3),
+            "batched_init_detail": {"boost_batch_init_s": round(lib_init_s, 3),
+                                    "workspace_alloc_s": round(alloc_s, 3),
+                                    "workspace_GB": round(bt_ws / 1e9, 1),
+                                    "constructor_total_s": round(init_s, 3),
+                                    "tuning": "cold (tuning cache cleared first)"},
             "schedule": {"requested": args.batch_schedule,
                          "key14": {"schedule": chosen[0][0], "segs_per_wg": chosen[0][1]},
                          "key15": {"schedule": chosen[1][0], "segs_per_wg": chosen[1][1]}},

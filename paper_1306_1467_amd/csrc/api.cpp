@@ -30,7 +30,7 @@ bool valid_options(const boost_options* o) {
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t keys, ii, ftab, sorder, w, wtmp, wpart, st, ring, perm, inv, wgbest, cls, pad, scratch, total;
+    size_t keys, ii, ftab, sorder, defer, w, wtmp, wpart, st, ring, perm, inv, wgbest, cls, pad, scratch, total;
 };
 
 static bool make_layout(int64_t n, const boost_feature_set* fs, Layout& L) {
@@ -44,6 +44,7 @@ static bool make_layout(int64_t n, const boost_feature_set* fs, Layout& L) {
     L.ii = take((size_t)P * (size_t)ii_stride_of(n) * 4);
     L.ftab = take((size_t)F * 4);
     L.sorder = take((size_t)F * 4);
+    L.defer = take(n > kNarrowMaxN ? (size_t)(F + 16) * 4 : 0);
     L.w = take((size_t)n * 16);
     L.wtmp = take((size_t)n * 8);
     L.wpart = take((size_t)kMaxPart * 8);
@@ -119,6 +120,7 @@ int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, cons
     h.scratch = sort_scratch_bytes(n) ? (uint64_t*)(ws + L.scratch) : nullptr;
 
     h.sorder = (const uint32_t*)(ws + L.sorder);
+    h.defer = n > kNarrowMaxN ? (uint32_t*)(ws + L.defer) : nullptr;
     std::vector<uint32_t> ftab((size_t)jd.F), sorder((size_t)jd.F);
     host_feature_table(fs, ftab.data());
     host_sort_order(ftab.data(), jd.F, sorder.data());
@@ -147,14 +149,14 @@ int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, cons
     h.n_pos = st.n_pos;
     if (ext == nullptr) {
         if ((rc = integral_launch(jd, d_images, s)) != BOOST_OK) return rc;
-        if ((rc = sort_launch(jd, h.sorder, h.scratch, num_cu, s)) != BOOST_OK) return rc;
+        if ((rc = sort_launch(jd, h.sorder, h.scratch, h.defer, num_cu, s)) != BOOST_OK) return rc;
     } else {
         const JobDev& old = *ext->old;
         if ((rc = extend_ii_launch(jd, old, d_images, s)) != BOOST_OK) return rc;
         const int64_t lm = st.n_pos - ext->l0;
         h.merged = n <= kMergeMaxN && old.g.narrow && old.g.lanes == jd.g.lanes;
         if (h.merged) rc = merge_launch(jd, h.sorder, old.keys, old.g, (int)ext->l0, (int)lm, num_cu, s);
-        else rc = sort_launch(jd, h.sorder, h.scratch, num_cu, s);
+        else rc = sort_launch(jd, h.sorder, h.scratch, h.defer, num_cu, s);
         if (rc != BOOST_OK) return rc;
     }
     if ((rc = init_weights_launch(jd, s)) != BOOST_OK) return rc;

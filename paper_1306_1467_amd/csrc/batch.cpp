@@ -3,6 +3,7 @@
 // from a captured HIP graph).
 #include <math.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -154,17 +155,11 @@ static int launch_part(boost_batch* b, int p) {
     return batch_scan_launch(b->part[p].kernel, b->part[p].grid, b->part[p].wg, b->bd, p, b->stream);
 }
 
-// Times one part's scan under its current configuration (the queue counter is
-// cleared before each launch; the other part is not launched).
-static int time_part(boost_batch* b, int p, double& ms) {
-    return time_launches(b->stream, kTuneRepsBatch, [&]() -> int {
-        VJB_HIP(hipMemsetAsync(b->bd.next_seg + p, 0, 4, b->stream));
-        return launch_part(b, p);
-    }, ms);
-}
-
-// Measured choice for one key format: first the schedule (with the default
-// segment granularity), then the segments per workgroup.
+// Measured choice for one key format, by successive halving: every schedule
+// (default segment granularity) is timed once, the three fastest twice more,
+// then the winner with the other segment granularities (twice each).  Each
+// configuration first runs a short untimed launch over its last `grid`
+// segments (instruction cache and first-launch costs); the minimum counts.
 static int tune_part(boost_batch* b, int p) {
     std::string key = "batch/" + tune_device_tag(b->device) + "/" + std::to_string(b->opts.precision) + "/" +
                       std::to_string(p);
@@ -180,30 +175,47 @@ static int tune_part(boost_batch* b, int p) {
         b->part[p] = cached;
         return upload_segments(b);
     }
+    auto time_cfg = [&](const PartCfg& pc, int reps, double& ms) -> int {
+        b->part[p] = pc;
+        int r = upload_segments(b);
+        if (r != BOOST_OK) return r;
+        VJB_HIP(hipMemsetAsync(b->bd.next_seg + p, 0, 4, b->stream));
+        if ((r = batch_scan_launch(pc.kernel, pc.grid, pc.wg, b->bd, p, b->stream, pc.grid)) != BOOST_OK) return r;
+        return time_launches(b->stream, reps, [&]() -> int {
+            VJB_HIP(hipMemsetAsync(b->bd.next_seg + p, 0, 4, b->stream));
+            return launch_part(b, p);
+        }, ms, false);
+    };
+    struct Cand { PartCfg pc; double ms; };
+    std::vector<Cand> cands;
     const int lanes = scan_schedule_lanes(b->part[p].schedule);
-    PartCfg best = b->part[p];
-    double best_ms = 1e300;
     for (int k = 0; k < scan_schedule_count(); ++k) {
         if (scan_schedule_lanes(k) != lanes) continue;
-        PartCfg pc;
-        if (part_config(pc, b->opts.precision, p == 0, k, b->num_cu) != BOOST_OK) continue;
-        b->part[p] = pc;
-        double ms = 0;
-        if ((rc = upload_segments(b)) != BOOST_OK || (rc = time_part(b, p, ms)) != BOOST_OK) return rc;
-        if (ms < best_ms) { best_ms = ms; best = pc; }
+        Cand c;
+        if (part_config(c.pc, b->opts.precision, p == 0, k, b->num_cu) != BOOST_OK) continue;
+        if ((rc = time_cfg(c.pc, 1, c.ms)) != BOOST_OK) return rc;
+        cands.push_back(c);
     }
-    static const int kSpw[] = {4, 8, 32};   // tried with the best schedule (kSegsPerWg was tried with each)
-    b->part[p] = best;
+    if (cands.empty()) { set_error("no batched scan schedule fits"); return BOOST_E_INVALID; }
+    std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+    if (cands.size() > 3) cands.resize(3);
+    for (Cand& c : cands) {
+        double ms = 0;
+        if ((rc = time_cfg(c.pc, 2, ms)) != BOOST_OK) return rc;
+        if (ms < c.ms) c.ms = ms;
+    }
+    Cand best = *std::min_element(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+    static const int kSpw[] = {4, 8, 32};   // besides the default kSegsPerWg
+    const PartCfg winner = best.pc;
     for (int spw : kSpw) {
-        PartCfg pc = best;
+        PartCfg pc = winner;
         pc.spw = spw;
-        b->part[p] = pc;
         double ms = 0;
-        if ((rc = upload_segments(b)) != BOOST_OK || (rc = time_part(b, p, ms)) != BOOST_OK) return rc;
-        if (ms < best_ms) { best_ms = ms; best = pc; }
+        if ((rc = time_cfg(pc, 2, ms)) != BOOST_OK) return rc;
+        if (ms < best.ms) { best.ms = ms; best.pc = pc; }
     }
-    b->part[p] = best;
-    tune_cache_put(key, {best.schedule, best.spw});
+    b->part[p] = best.pc;
+    tune_cache_put(key, {best.pc.schedule, best.pc.spw});
     return upload_segments(b);
 }
 

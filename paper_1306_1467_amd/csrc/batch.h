@@ -31,7 +31,10 @@ constexpr int kMaxJobs = 4096;
 
 const void* batch_scan_kernel(int precision, bool narrow, int schedule);
 // part 0: the 14-bit-key jobs' segments, part 1: the 15-bit ones
-int batch_scan_launch(const void* kernel, int grid, int wg, const BatchDev& b, int part, hipStream_t s);
+// last > 0: only the part's last `last` segments (a short warm-up launch of
+// the tuner; the other segments' results are left as they were).
+int batch_scan_launch(const void* kernel, int grid, int wg, const BatchDev& b, int part, hipStream_t s,
+                      int last = 0);
 int batch_update_launch(int precision, int n_upd, const BatchDev& b, hipStream_t s);
 int batch_gather_launch(const BatchDev& b, int n_jobs, int64_t first, int count, boost_stump* out, hipStream_t s);
 

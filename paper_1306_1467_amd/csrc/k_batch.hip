@@ -109,10 +109,11 @@ const void* batch_scan_kernel(int precision, bool narrow, int schedule) {
     }
 }
 
-int batch_scan_launch(const void* kernel, int grid, int wg, const BatchDev& b, int part, hipStream_t s) {
+int batch_scan_launch(const void* kernel, int grid, int wg, const BatchDev& b, int part, hipStream_t s, int last) {
     uint32_t* ctr = b.next_seg + part;
     int s_begin = part == 0 ? 0 : b.seg_split;
     int s_end = part == 0 ? b.seg_split : b.n_segs;
+    if (last > 0 && s_end - last > s_begin) s_begin = s_end - last;
     void* args[] = {(void*)&b.jobs, (void*)&b.segs, (void*)&ctr, (void*)&s_begin, (void*)&s_end, (void*)&b.job_seg,
                     (void*)&b.seg_best};
     VJB_HIP(hipLaunchKernel(kernel, dim3((unsigned)grid), dim3((unsigned)wg), args, 0, s));

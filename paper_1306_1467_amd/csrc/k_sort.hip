@@ -173,7 +173,8 @@ __device__ __forceinline__ void scan_counts(uint16_t* cnt, int m, uint32_t* wtot
 }
 
 template <int NT, int C>
-__global__ __launch_bounds__(NT) void k_sort(JobDev jd, int64_t npow2, int ib, uint64_t* __restrict__ scratch) {
+__global__ __launch_bounds__(NT) void k_sort(JobDev jd, int64_t npow2, int ib, uint64_t* __restrict__ scratch,
+                                             const uint32_t* __restrict__ list) {
     constexpr int NW = NT / 64;
     constexpr int NCNT = kDigits * C * NW;                 // counters in (digit, slot, wave) order
     constexpr int E = (NCNT + NT - 1) / NT;                 // counters per thread in the scan
@@ -185,7 +186,10 @@ __global__ __launch_bounds__(NT) void k_sort(JobDev jd, int64_t npow2, int ib, u
     const int wp1 = jd.W + 1;
     const uint32_t imask = (1u << ib) - 1u;
     uint16_t* cnt = (uint16_t*)(buf + NT * C);
-    for (int64_t j = blockIdx.x; j < jd.F; j += gridDim.x) {
+    // every feature, or (list != NULL) the list[0] features list[16 + t]
+    const int64_t count = list != nullptr ? (int64_t)list[0] : jd.F;
+    for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
+        const int64_t j = list != nullptr ? (int64_t)list[16 + t] : t;
         const uint32_t desc = jd.ftab[j];
         // values go through the LDS buffer (bounded register use), then the
         // packed words into registers
@@ -351,24 +355,33 @@ struct CntScratch {
 // current order).  Each pass scatters into buf (NT * C words) and reloads;
 // on return it[] and buf hold the sorted order (buf untouched when no pass
 // runs).  The caller must have finished reading buf (a barrier) before the
-// call; the call ends with buf complete (after a barrier).
+// call; the call ends with buf complete (after a barrier).  A thread counts
+// its items' digits in groups of at most 15 items (16 4-bit fields per
+// group).
 template <int NT, int C>
 __device__ __forceinline__ void cnt_sort_passes(uint32_t* it, uint32_t* buf, CntScratch<NT>& cs, int sh0, int sh1) {
-    static_assert(C <= 15 && (C & 1) == 1, "4-bit counters; odd C keeps the chunk reads conflict-free");
+    static_assert(C <= 31 && (C & 1) == 1, "at most 31 items a thread; odd C keeps the chunk reads conflict-free");
+    constexpr int NG = (C + 14) / 15;   // counter groups
     constexpr int NW = NT / 64;
     static_assert(16 * NW <= 256, "one wave scans the (digit, wave) totals, four per lane");
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int sh = sh0; sh < sh1; sh += 4) {
-        // 1. counts: 16 4-bit fields
-        uint64_t cnt = 0;
+        // 1. counts: 16 4-bit fields per group of items
+        uint64_t cnt[NG];
 #pragma unroll
-        for (int k = 0; k < C; ++k) cnt += 1ull << (4 * ((it[k] >> sh) & 15u));
+        for (int g = 0; g < NG; ++g) cnt[g] = 0;
+#pragma unroll
+        for (int k = 0; k < C; ++k) cnt[k / 15] += 1ull << (4 * ((it[k] >> sh) & 15u));
         // 2. scan across the wave (digits 2p, 2p + 1 in word p), then across (digit, wave)
         uint32_t ex[8];
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
-            const uint32_t c2 = (uint32_t)(cnt >> (8 * p));
-            const uint32_t f = (c2 & 0xFu) | ((c2 & 0xF0u) << 12);
+            uint32_t f = 0;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const uint32_t c2 = (uint32_t)(cnt[g] >> (8 * p));
+                f += (c2 & 0xFu) | ((c2 & 0xF0u) << 12);
+            }
             const uint32_t inc = wave_scan_incl(f);
             ex[p] = inc - f;
             if (lane == 63) cs.wtot[wv][p] = inc;
@@ -408,8 +421,11 @@ __device__ __forceinline__ void cnt_sort_passes(uint32_t* it, uint32_t* buf, Cnt
         }
 #pragma unroll
         for (int k = 0; k < C; ++k) {
+            if (k % 15 == 0) run = 0;   // the rank counts restart with each group ...
             const uint32_t d = (it[k] >> sh) & 15u;
-            const uint32_t r = (uint32_t)(run >> (4 * d)) & 15u;
+            uint32_t r = (uint32_t)(run >> (4 * d)) & 15u;
+#pragma unroll
+            for (int g = 0; g < k / 15; ++g) r += (uint32_t)(cnt[g] >> (4 * d)) & 15u;   // ... after the earlier groups
             run += 1ull << (4 * d);
             buf[cs.tab[d * NT + tid] + r] = it[k];
         }
@@ -418,6 +434,26 @@ __device__ __forceinline__ void cnt_sort_passes(uint32_t* it, uint32_t* buf, Cnt
         for (int k = 0; k < C; ++k) it[k] = buf[tid * C + k];
     }
     __syncthreads();
+}
+
+// Values of windows k NT + threadIdx.x (k < C, below n) of a feature of type
+// TYPE stored to s[window] in LDS; their minimum and maximum over this
+// thread's windows in vmin / vmax.  Partly unrolled: a full unroll of 31
+// slots spills registers.
+template <int TYPE, int NT, int C>
+__device__ __forceinline__ void eval_windows_lds(const int32_t* __restrict__ ii, int64_t S, int wp1, int x, int y,
+                                                 int cw, int ch, int n, uint32_t* s, int32_t& vmin,
+                                                 int32_t& vmax) {
+#pragma unroll 5
+    for (int k = 0; k < C; ++k) {
+        const int i = k * NT + threadIdx.x;
+        if (i < n) {
+            const int32_t v = haar_value_t<TYPE>(ii, S, wp1, x, y, cw, ch, i);
+            s[i] = (uint32_t)v;
+            vmin = v < vmin ? v : vmin;
+            vmax = v > vmax ? v : vmax;
+        }
+    }
 }
 
 // Values of feature `desc` on windows k NT + threadIdx.x, k < C: the loads
@@ -433,6 +469,38 @@ __device__ __forceinline__ void eval_values(const JobDev& jd, uint32_t desc, int
     case BOOST_TYPE_2H: eval_windows<BOOST_TYPE_2H, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
     case BOOST_TYPE_2V: eval_windows<BOOST_TYPE_2V, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
     default: eval_windows<BOOST_TYPE_4, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
+    }
+}
+
+// Values of feature `desc` on the first n windows into s[0 .. n) (LDS), and
+// their range (every thread gets the same; one barrier).
+template <int NT, int C>
+__device__ __forceinline__ void eval_to_lds(const JobDev& jd, uint32_t desc, int n, uint32_t* s, int32_t* rmin,
+                                            int32_t* rmax, int32_t& vmin, int32_t& vmax) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wp1 = jd.W + 1;
+    int t, x, y, cw, ch;
+    unpack_feature(desc, t, x, y, cw, ch);
+    vmin = INT_MAX;
+    vmax = INT_MIN;
+    switch (t) {
+    case BOOST_TYPE_3H: eval_windows_lds<BOOST_TYPE_3H, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, s, vmin, vmax); break;
+    case BOOST_TYPE_3V: eval_windows_lds<BOOST_TYPE_3V, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, s, vmin, vmax); break;
+    case BOOST_TYPE_2H: eval_windows_lds<BOOST_TYPE_2H, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, s, vmin, vmax); break;
+    case BOOST_TYPE_2V: eval_windows_lds<BOOST_TYPE_2V, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, s, vmin, vmax); break;
+    default: eval_windows_lds<BOOST_TYPE_4, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, s, vmin, vmax); break;
+    }
+    vmin = wave_ext<false>(vmin);
+    vmax = wave_ext<true>(vmax);
+    if (lane == 0) { rmin[wv] = vmin; rmax[wv] = vmax; }
+    __syncthreads();
+    vmin = rmin[0];
+    vmax = rmax[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        vmin = rmin[w] < vmin ? rmin[w] : vmin;
+        vmax = rmax[w] > vmax ? rmax[w] : vmax;
     }
 }
 
@@ -488,9 +556,15 @@ struct SortCntLds {
 };
 
 // One feature per workgroup at a time, in the visiting order sorder.
+//
+// defer (NULL when every value range fits beside the index, i.e. ib <= 14):
+// a feature whose packed words would need more than 32 bits is not sorted
+// here; its index goes to defer[16 + c] with c = atomicAdd(defer, 1), for
+// the 64-bit path (k_sort over that list).
 template <int NT, int C>
 __global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, const uint32_t* __restrict__ ftab,
-                                                 const uint32_t* __restrict__ sorder, int ib) {
+                                                 const uint32_t* __restrict__ sorder, int ib,
+                                                 uint32_t* __restrict__ defer) {
     constexpr int U = (C + 7) / 8;   // key units per thread: ceil(n / 8) <= U NT
     extern __shared__ __align__(16) unsigned char smem[];
     SortCntLds<NT, C>& L = *reinterpret_cast<SortCntLds<NT, C>*>(smem);
@@ -498,26 +572,52 @@ __global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, const uint32_t* __re
     const int n = (int)jd.g.n;
     for (FeatureWalk wk = feature_walk(jd.F); wk.p < wk.end; wk.p += wk.step) {
         const int64_t j = sorder[wk.p];
-        int32_t v[C], vmin, vmax;
-#if VJB_EXP_VDESC
-        eval_values<NT, C>(jd, jd.ftab[j], n, v);
+        // values: in registers (up to 15 a thread), else through LDS
+        int32_t vmin, vmax;
+        int32_t v[C <= 15 ? C : 1];
+#ifndef VJB_EXP_LDSEVAL
+        constexpr bool kRegs = C <= 15;
 #else
-        eval_values<NT, C>(jd, ftab[j], n, v);
+        constexpr bool kRegs = false;
 #endif
-        value_range<NT, C>(v, n, L.rmin, L.rmax, vmin, vmax);
-        const uint32_t range = (uint32_t)(vmax - vmin);
-        const int rb = range == 0 ? 0 : 32 - __clz(range);   // <= 18 for windows up to 32x32, ib <= 14
-        // packed words in index order; positions past n hold all-ones
-        // sentinels (digit 15 in every pass, behind every window)
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const int i = k * NT + tid;
-            L.buf[i] = i < n ? (((uint32_t)(v[k] - vmin)) << ib) | (uint32_t)i : 0xFFFFFFFFu;
+        if constexpr (kRegs) {
+            eval_values<NT, C>(jd, ftab[j], n, v);
+            value_range<NT, C>(v, n, L.rmin, L.rmax, vmin, vmax);
+        } else {
+            eval_to_lds<NT, C>(jd, ftab[j], n, L.buf, L.rmin, L.rmax, vmin, vmax);
         }
-        __syncthreads();
+        const uint32_t range = (uint32_t)(vmax - vmin);
+        const int rb = range == 0 ? 0 : 32 - __clz(range);   // <= 18 for windows up to 32x32
+        if (defer != nullptr && rb + ib > 32) {   // uniform across the workgroup
+            if (tid == 0) defer[16 + atomicAdd(defer, 1u)] = (uint32_t)j;
+            __syncthreads();   // every thread has read the range before the next feature's
+            continue;
+        }
+        // this thread's chunk (windows tC .. tC + C - 1) as packed words;
+        // positions past n are all-ones sentinels (digit 15 in every pass,
+        // behind every window)
         uint32_t it[C];
+        if constexpr (kRegs) {
 #pragma unroll
-        for (int k = 0; k < C; ++k) it[k] = L.buf[tid * C + k];
+            for (int k = 0; k < C; ++k) {
+                const int i = k * NT + tid;
+                L.buf[i] = i < n ? (((uint32_t)(v[k] - vmin)) << ib) | (uint32_t)i : 0xFFFFFFFFu;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < C; ++k) it[k] = L.buf[tid * C + k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                const int i = tid * C + k;
+                it[k] = i < n ? ((L.buf[i] - (uint32_t)vmin) << ib) | (uint32_t)i : 0xFFFFFFFFu;
+            }
+            if (rb == 0) {   // no pass: the words are already in order
+#pragma unroll
+                for (int k = 0; k < C; ++k) L.buf[tid * C + k] = it[k];
+                __syncthreads();
+            }
+        }
         cnt_sort_passes<NT, C>(it, L.buf, L.cs, ib, ib + rb);
 #pragma unroll
         for (int k = 0; k < U; ++k) {
@@ -679,7 +779,7 @@ int merge_launch(const JobDev& jd, const uint32_t* sorder, const uint4* old_keys
 }
 
 template <int NT, int C>
-static int sort_cnt_launch(const JobDev& jd, const uint32_t* sorder, int num_cu, hipStream_t s) {
+static int sort_cnt_launch(const JobDev& jd, const uint32_t* sorder, uint32_t* defer, int num_cu, hipStream_t s) {
     const int64_t n = jd.g.n;
     int ib = n <= 1 ? 1 : 32 - __builtin_clz((unsigned)(n - 1));
     const size_t lds = sizeof(SortCntLds<NT, C>);
@@ -696,13 +796,13 @@ static int sort_cnt_launch(const JobDev& jd, const uint32_t* sorder, int num_cu,
     if (grid > kMaxSortGrid) grid = kMaxSortGrid;
     JobDev a = jd;
     const uint32_t* ftab = jd.ftab;
-    void* args[] = {(void*)&a, (void*)&ftab, (void*)&sorder, (void*)&ib};
+    void* args[] = {(void*)&a, (void*)&ftab, (void*)&sorder, (void*)&ib, (void*)&defer};
     VJB_HIP(hipLaunchKernel(k, dim3((unsigned)grid), dim3(NT), args, lds, s));
     return BOOST_OK;
 }
 
 template <int NT, int C>
-static int sort_launch_c(const JobDev& jd, uint64_t* scratch, int num_cu, hipStream_t s) {
+static int sort_launch_c(const JobDev& jd, uint64_t* scratch, const uint32_t* list, int num_cu, hipStream_t s) {
     const int64_t n = jd.g.n;
     int64_t npow2 = sort_pow2(n);
     int ib = n <= 1 ? 1 : 32 - __builtin_clz((unsigned)(n - 1));
@@ -723,28 +823,35 @@ static int sort_launch_c(const JobDev& jd, uint64_t* scratch, int num_cu, hipStr
         return BOOST_E_INVALID;
     }
     JobDev a = jd;
-    void* args[] = {(void*)&a, (void*)&npow2, (void*)&ib, (void*)&scratch};
+    void* args[] = {(void*)&a, (void*)&npow2, (void*)&ib, (void*)&scratch, (void*)&list};
     VJB_HIP(hipLaunchKernel(k, dim3((unsigned)grid), dim3(NT), args, lds, s));
     return BOOST_OK;
 }
 
 // Counting-sort passes up to 15,360 windows (C values per thread, the
 // smallest odd C of the shape that covers n); ballot-ranked passes beyond.
-int sort_launch(const JobDev& jd, const uint32_t* sorder, uint64_t* scratch, int num_cu, hipStream_t s) {
+int sort_launch(const JobDev& jd, const uint32_t* sorder, uint64_t* scratch, uint32_t* defer, int num_cu,
+                hipStream_t s) {
     const int64_t n = jd.g.n;
-    if (n <= 256 * 7) return sort_cnt_launch<256, 7>(jd, sorder, num_cu, s);
-    if (n <= 512 * 7) return sort_cnt_launch<512, 7>(jd, sorder, num_cu, s);
-    if (n <= 1024 * 7) return sort_cnt_launch<1024, 7>(jd, sorder, num_cu, s);
-    if (n <= 1024 * 11) return sort_cnt_launch<1024, 11>(jd, sorder, num_cu, s);
-    if (n <= 1024 * 15) return sort_cnt_launch<1024, 15>(jd, sorder, num_cu, s);
-    if (n <= 256) return sort_launch_c<256, 1>(jd, scratch, num_cu, s);
-    if (n <= 512) return sort_launch_c<256, 2>(jd, scratch, num_cu, s);
-    if (n <= 1024) return sort_launch_c<256, 4>(jd, scratch, num_cu, s);
-    if (n <= 2048) return sort_launch_c<256, 8>(jd, scratch, num_cu, s);
-    if (n <= 4096) return sort_launch_c<1024, 4>(jd, scratch, num_cu, s);
-    if (n <= 8192) return sort_launch_c<1024, 8>(jd, scratch, num_cu, s);
-    if (n <= 16384) return sort_launch_c<1024, 16>(jd, scratch, num_cu, s);
-    if (n <= 32768) return sort_launch_c<512, 64>(jd, scratch, num_cu, s);
+    if (n <= 256 * 7) return sort_cnt_launch<256, 7>(jd, sorder, nullptr, num_cu, s);
+    if (n <= 512 * 7) return sort_cnt_launch<512, 7>(jd, sorder, nullptr, num_cu, s);
+    if (n <= 1024 * 7) return sort_cnt_launch<1024, 7>(jd, sorder, nullptr, num_cu, s);
+    if (n <= 1024 * 11) return sort_cnt_launch<1024, 11>(jd, sorder, nullptr, num_cu, s);
+    if (n <= 1024 * 15) return sort_cnt_launch<1024, 15>(jd, sorder, nullptr, num_cu, s);
+    if (n <= kNarrowMaxN + 1) return sort_cnt_launch<1024, 31>(jd, sorder, nullptr, num_cu, s);   // 14-bit indices
+    if (n <= 1024 * 31) {
+        // 15-bit indices: features whose values span more than 17 bits go
+        // through the 64-bit path, listed by the counting sort
+        if (defer == nullptr || scratch == nullptr) {
+            set_error("sort: the defer list or the fallback scratch is missing");
+            return BOOST_E_INVALID;
+        }
+        VJB_HIP(hipMemsetAsync(defer, 0, 4, s));
+        int rc = sort_cnt_launch<1024, 31>(jd, sorder, defer, num_cu, s);
+        if (rc != BOOST_OK) return rc;
+        return sort_launch_c<512, 64>(jd, scratch, defer, num_cu, s);
+    }
+    if (n <= 32768) return sort_launch_c<512, 64>(jd, scratch, nullptr, num_cu, s);
     set_error("too many windows for the sort");
     return BOOST_E_INVALID;
 }

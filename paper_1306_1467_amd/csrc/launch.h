@@ -25,7 +25,16 @@ struct ScanPlan {
 };
 
 // api.cpp: one job's layout and one-time preparation (shared by the batch)
-struct JobHost { JobDev jd; double* wtmp; StumpDev* cls; uint64_t* scratch; const uint32_t* sorder; int64_t n_pos; bool merged; };
+struct JobHost {
+    JobDev jd;
+    double* wtmp;
+    StumpDev* cls;
+    uint64_t* scratch;       // the 64-bit sort path's scratch (n > kNarrowMaxN), else NULL
+    const uint32_t* sorder;  // the order the one-time preparation visits the features
+    uint32_t* defer;         // features left to the 64-bit sort path (n > kNarrowMaxN), else NULL
+    int64_t n_pos;
+    bool merged;
+};
 // A prepared job that a new job extends: the new job's windows are the old
 // job's (in its caller order) followed by the new ones.
 struct ExtendSrc { const JobDev* old; int64_t l0; };
@@ -54,7 +63,6 @@ int probe_launch(const ScanPlan& p, int schedule, const JobDev& jd, uint32_t* si
 
 // tune.cpp: measured schedule choice
 constexpr int kTuneReps = 5;        // timed launches per candidate of a single job (the minimum counts)
-constexpr int kTuneRepsBatch = 3;   // the same for a batch (its launches are longer)
 constexpr double kTunePrune = 1.03;  // a single job's candidates this much slower than the best stop after two rounds
 // Runs launch() once untimed (when warm), then `reps` times each bracketed by
 // HIP events on s; best_ms is the fastest.
@@ -99,6 +107,9 @@ int merge_launch(const JobDev& jd, const uint32_t* sorder, const uint4* old_keys
 // k_sort.hip
 int64_t sort_pow2(int64_t n);
 size_t sort_scratch_bytes(int64_t n);
-int sort_launch(const JobDev& jd, const uint32_t* sorder, uint64_t* scratch, int num_cu, hipStream_t s);
+// defer: F + 16 words for jobs of more than kNarrowMaxN windows (the features
+// the counting sort leaves to the 64-bit path), NULL otherwise.
+int sort_launch(const JobDev& jd, const uint32_t* sorder, uint64_t* scratch, uint32_t* defer, int num_cu,
+                hipStream_t s);
 
 }  // namespace vjb

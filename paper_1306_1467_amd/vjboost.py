@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import time
 
 import numpy as np
 
@@ -586,9 +587,13 @@ class BatchTrainer:
         self.ws_bytes = boost_batch_workspace_bytes(arr, self.opts)
         if self.ws_bytes == 0:
             raise BoostError(BOOST_E_INVALID, last_error())
+        t0 = time.perf_counter()
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         torch.cuda.synchronize(self.device)
+        self.alloc_s = time.perf_counter() - t0   # the caller's workspace allocation
+        t0 = time.perf_counter()
         self.ctx = boost_batch_init(arr, self.opts, self.workspace, self.ws_bytes)
+        self.init_s = time.perf_counter() - t0    # boost_batch_init (it synchronises)
 
     def sync(self):
         self.stream.synchronize()

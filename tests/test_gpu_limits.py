@@ -1,7 +1,9 @@
 """Size limits: the largest job (32,767 windows, which fills the 15-bit key
 format and its 32,768-entry weight table), the boundary between the 14-bit
-and 15-bit key formats (16,383 / 16,384 windows), and the FP64 table limit
-(20,000 windows).  Values, sorted keys and two teacher-forced rounds are
+and 15-bit key formats (16,383 / 16,384 windows), the largest job the
+counting sort takes with 31 windows a thread (31,744) and the first one past
+it (31,745), a job in between (24,000), and the FP64 table limit (20,000
+windows).  Values, sorted keys and two teacher-forced rounds are
 compared with the oracle (FP32 weights with FP64 or compensated sums; plain
 FP32 is covered at small sizes, where its error bound is tight)."""
 import sys
@@ -27,7 +29,7 @@ def say(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module", params=[32767, 16384, 16383])
+@pytest.fixture(scope="module", params=[32767, 31745, 31744, 24000, 16384, 16383])
 def big(request):
     n = request.param
     images, labels = synth.small_job((500, n), n, 6, 8)
