@@ -400,6 +400,48 @@ def run_batched(name, precision, args, torch, vb, specs, data):
             "stumps_identical_to_plain": bool(same)}
 
 
+def retrain_report(torch, vb, images, labels, precision: str, n0: int = 10000, fracs=(0.01, 0.1, 0.5)):
+    """Incremental retraining: a context prepared on n0 windows of the
+    headline workload, extended by m = frac * n0 more (boost_extend, which
+    reuses the old windows' key order), against a fresh boost_init on the same
+    n0 + m windows.  Library times only (the workspace allocations are the
+    caller's); schedule fixed, so no tuning in either.  The extended context's
+    sorted keys (a sample of features) and first 3 rounds must equal the
+    fresh one's."""
+    import numpy as np
+    p = np.random.default_rng(957).permutation(len(labels))
+    img, lab = np.ascontiguousarray(images[p]), np.ascontiguousarray(labels[p])
+    sched = 9
+    base = vb.Trainer(torch.from_numpy(img[:n0]), torch.from_numpy(lab[:n0]), precision=precision,
+                      schedule_id=sched)
+    out = {"base_windows": n0, "precision": precision, "schedule": sched, "base_init_ms": round(base.init_s * 1e3, 2),
+           "cases": []}
+    for f in fracs:
+        m = int(round(f * n0))
+        union_img, union_lab = img[:n0 + m], lab[:n0 + m]
+        ext = base.extend(torch.from_numpy(img[n0:n0 + m]), torch.from_numpy(lab[n0:n0 + m]))
+        fresh = vb.Trainer(torch.from_numpy(union_img), torch.from_numpy(union_lab), precision=precision,
+                           schedule_id=sched)
+        same = True
+        for j0 in (0, fresh.F // 3, fresh.F - 2048):
+            oe, fe = ext.sorted(j0, 2048)
+            of, ff = fresh.sorted(j0, 2048)
+            same &= bool(torch.equal(oe, of) and torch.equal(fe, ff))
+        same &= ext.train(3).tobytes() == fresh.train(3).tobytes()
+        out["cases"].append({"added_windows": m, "added_frac": f, "merged": ext.merged(),
+                             "extend_ms": round(ext.init_s * 1e3, 2), "fresh_init_ms": round(fresh.init_s * 1e3, 2),
+                             "speedup": round(fresh.init_s / ext.init_s, 2), "identical_to_fresh": same})
+        progress(f"retrain +{m} windows: extend {ext.init_s * 1e3:.1f} ms, fresh {fresh.init_s * 1e3:.1f} ms")
+        for t in (ext, fresh):
+            t.close()
+        del ext, fresh
+        torch.cuda.empty_cache()
+    base.close()
+    del base
+    torch.cuda.empty_cache()
+    return out
+
+
 def classifier_report(torch, vb, synth, images, labels, precision: str, rounds: int):
     """The strong classifier of `rounds` stumps: training-error curve and the
     error on held-out windows of the same recipe (seeded apart)."""
@@ -464,7 +506,8 @@ def main():
     ap.add_argument("--batch-rounds", type=int, default=0, help="rounds per batched job (0: the workload's own)")
     ap.add_argument("--batch-schedule", type=int, default=-1,
                     help="schedule of the batched and the plain per-job runs (-1: measured choice at init)")
-    ap.add_argument("--classifier-rounds", type=int, default=200)
+    ap.add_argument("--classifier-rounds", type=int, default=200, help="0 skips the strong-classifier report")
+    ap.add_argument("--no-retrain", action="store_true", help="skip the incremental-retraining timings")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run one device copy of this many GiB first (counter calibration)")
     ap.add_argument("--prep-only", action="store_true",
@@ -540,9 +583,12 @@ def main():
     if sweep:
         line["precision_sweep"] = run_precision_sweep(args, torch, vb, images, labels, res["F"], res["n"], sweep)
         progress("precision sweep done")
-    line["strong_classifier"] = classifier_report(torch, vb, synth, images, labels, args.precision,
-                                                  args.classifier_rounds)
-    progress("strong classifier done")
+    if args.classifier_rounds > 0:
+        line["strong_classifier"] = classifier_report(torch, vb, synth, images, labels, args.precision,
+                                                      args.classifier_rounds)
+        progress("strong classifier done")
+    if not args.no_retrain:
+        line["incremental_retraining"] = retrain_report(torch, vb, images, labels, args.precision)
     headline_tables = None
     if args.precision_rounds > 0 or not args.no_cpu_baseline:
         headline_tables = oracle_tables(images, None, host_threads)

@@ -441,7 +441,9 @@ class Trainer:
             raise BoostError(BOOST_E_INVALID, last_error())
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         torch.cuda.synchronize(self.device)
+        t0 = time.perf_counter()
         self.ctx = boost_init(self.images, self.labels, self.n, self.fs, self.opts, self.workspace, self.ws_bytes)
+        self.init_s = time.perf_counter() - t0    # boost_init (it synchronises)
 
     def extend(self, images, labels):
         """A new Trainer over this trainer's windows followed by `images` /
@@ -465,7 +467,9 @@ class Trainer:
             raise BoostError(BOOST_E_INVALID, last_error())
         new.workspace = torch.empty(new.ws_bytes, dtype=torch.uint8, device=self.device)
         torch.cuda.synchronize(self.device)
+        t0 = time.perf_counter()
         new.ctx = boost_extend(self.ctx, new.images, new.labels, m, new.workspace, new.ws_bytes)
+        new.init_s = time.perf_counter() - t0     # boost_extend (it synchronises)
         return new
 
     def merged(self) -> bool:
