@@ -199,10 +199,11 @@ int boost_init(boost_ctx **out, const uint8_t *d_images, const uint8_t *d_labels
  * integral images, feature values, sorted keys and initial weights (Table 2
  * over the union), so training continues as from a fresh boost_init.  The
  * paper's case for a distributed trainer is fast retraining when the
- * training set changes (Abstract, Section 1.1); here the old windows' value
- * order is reused: only the new windows are sorted and merged into each
- * feature's order (unions up to 15,360 windows; larger ones are sorted in
- * full), the old windows' integral images are copied.
+ * training set changes (Abstract, Section 1.1).  The old windows' integral
+ * images are copied.  For m <= 512 new windows and a union of at most 15,360,
+ * the old windows' value order is reused: only the new windows are put in
+ * order and merged into each feature's order.  Any other union is sorted in
+ * full, which is faster there (the merge still evaluates every window).
  *   c              a prepared context (not modified; it stays valid).
  *   d_images       m new windows, window_h x window_w uint8 row-major (device).
  *   d_labels       m labels 0/1 (device).

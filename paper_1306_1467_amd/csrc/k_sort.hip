@@ -652,25 +652,42 @@ struct MergeArgs {
     int32_t rb_off, x_off;   // LDS byte offsets of the new words' buffer and of the shared region
 };
 
-template <int CB>
-__global__ __launch_bounds__(1024) void k_merge(JobDev jd, const uint32_t* __restrict__ sorder, MergeArgs ma) {
-    constexpr int NT = 1024, C = 15;
+// C: window slots a thread holds (n <= 1024 C).  The new windows (m <= 512)
+// are put in order by counting: each new word's rank among the new words is
+// the number of new words below it (one comparison pass over the m words,
+// no barriers; the counting-sort passes cost more than this at such sizes,
+// and more than sorting the whole union once m passes about 512).
+template <int C>
+__global__ __launch_bounds__(1024) void k_merge(JobDev jd, const uint32_t* __restrict__ ftab,
+                                               const uint32_t* __restrict__ sorder, MergeArgs ma) {
+    constexpr int NT = 1024;
+    constexpr int OU = 2;                                    // old units a thread reads (ceil(n0 / 8) <= 2 NT)
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* buf = (uint32_t*)smem;                         // NT * C words: index order, then the merged order
-    uint32_t* rbuf = (uint32_t*)(smem + ma.rb_off);          // NT * CB words: the new windows' order
-    CntScratch<NT>& cs = *(CntScratch<NT>*)(smem + ma.x_off);   // during the passes ...
-    uint32_t* abuf = (uint32_t*)(smem + ma.x_off);           // ... then the old windows' order
+    uint32_t* rbuf = (uint32_t*)(smem + ma.rb_off);          // the new windows' words in order
+    uint32_t* abuf = (uint32_t*)(smem + ma.x_off);           // the old windows' words in the old order
     __shared__ int32_t rmin[NT / 64], rmax[NT / 64];
     const int tid = threadIdx.x;
     const int n = (int)jd.g.n;           // n0 + m
     const int mn = ma.m - ma.lm;         // new negatives: union indices n - mn .. n - 1
     const int E = (n + NT - 1) / NT;
     const KeyGeom& og = ma.og;
+    const int olsh = __builtin_ctz((unsigned)og.lanes);
+    auto new_index = [&](int p) { return p < ma.lm ? ma.l0 + p : n - mn + (p - ma.lm); };
     for (FeatureWalk wk = feature_walk(jd.F); wk.p < wk.end; wk.p += wk.step) {
         const int64_t j = sorder[wk.p];
-        // 1.
+        // the old keys of this feature, issued first so that their loads
+        // overlap the evaluation (memory unit mu of the old row holds
+        // rank-order unit start(L) + r of lane L = mu % lanes, r = mu / lanes)
+        uint4 oq[OU];
+#pragma unroll
+        for (int k = 0; k < OU; ++k) {
+            const int mu = tid + k * NT;
+            oq[k] = mu < (int)og.nc ? ma.old_keys[j * og.row_units + mu] : make_uint4(0, 0, 0, 0);
+        }
+        // 1. the union's values and packed words in index order
         int32_t v[C], vmin, vmax;
-        eval_values<NT, C>(jd, jd.ftab[j], n, v);
+        eval_values<NT, C>(jd, ftab[j], n, v);
         value_range<NT, C>(v, n, rmin, rmax, vmin, vmax);
         const uint32_t range = (uint32_t)(vmax - vmin);
         const int rb = range == 0 ? 0 : 32 - __clz(range);
@@ -680,29 +697,30 @@ __global__ __launch_bounds__(1024) void k_merge(JobDev jd, const uint32_t* __res
             if (i < n) buf[i] = (((uint32_t)(v[k] - vmin)) << ma.ib) | (uint32_t)i;
         }
         __syncthreads();
-        // 2. the new windows, index order: union indices l0 .. l0 + lm - 1, then n - mn .. n - 1
-        uint32_t it[CB];
-#pragma unroll
-        for (int k = 0; k < CB; ++k) {
-            const int p = tid * CB + k;
-            it[k] = p < ma.m ? buf[p < ma.lm ? ma.l0 + p : n - mn + (p - ma.lm)] : 0xFFFFFFFFu;
-            rbuf[p] = it[k];
+        // 2. the new windows in order (union indices l0 .. l0 + lm - 1, then n - mn .. n - 1)
+        (void)rb;
+        if (tid < ma.m) {
+            const uint32_t x = buf[new_index(tid)];
+            int r = 0;
+            for (int q = 0; q < ma.m; ++q) r += buf[new_index(q)] < x ? 1 : 0;   // words are unique
+            rbuf[r] = x;
         }
-        __syncthreads();
-        cnt_sort_passes<NT, CB>(it, rbuf, cs, ma.ib, ma.ib + rb);
         // 3. the old windows in the old order
-        for (int u = tid; u < (int)og.nc; u += NT) {
-            const int L = u < (og.q + 1) * og.rem ? u / (og.q + 1) : og.rem + (u - (og.q + 1) * og.rem) / og.q;
-            const int r = u - (L * og.q + (L < og.rem ? L : og.rem));   // unit within lane L's segment
-            const uint4 q4 = ma.old_keys[j * og.row_units + (int64_t)r * og.lanes + L];
-            const uint32_t dw[4] = {q4.x, q4.y, q4.z, q4.w};
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                uint32_t i0, f0, i1, f1;
-                decode_pair(og.narrow, dw[h], i0, f0, i1, f1);
-                const int r0 = 8 * u + 2 * h;
-                if (r0 < ma.n0) abuf[r0] = buf[(int)i0 < ma.l0 ? i0 : i0 + ma.lm];
-                if (r0 + 1 < ma.n0) abuf[r0 + 1] = buf[(int)i1 < ma.l0 ? i1 : i1 + ma.lm];
+        for (int k = 0; k < OU; ++k) {
+            const int mu = tid + k * NT;
+            if (mu < (int)og.nc) {
+                const int L = mu & (og.lanes - 1);
+                const int u = L * og.q + (L < og.rem ? L : og.rem) + (mu >> olsh);
+                const uint32_t dw[4] = {oq[k].x, oq[k].y, oq[k].z, oq[k].w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    uint32_t i0, f0, i1, f1;
+                    decode_pair(og.narrow, dw[h], i0, f0, i1, f1);
+                    const int r0 = 8 * u + 2 * h;
+                    if (r0 < ma.n0) abuf[r0] = buf[(int)i0 < ma.l0 ? i0 : i0 + ma.lm];
+                    if (r0 + 1 < ma.n0) abuf[r0 + 1] = buf[(int)i1 < ma.l0 ? i1 : i1 + ma.lm];
+                }
             }
         }
         __syncthreads();
@@ -727,7 +745,7 @@ __global__ __launch_bounds__(1024) void k_merge(JobDev jd, const uint32_t* __res
                     else { ++b; wb = b < ma.m ? rbuf[b] : 0xFFFFFFFFu; }
                 }
             }
-            __syncthreads();   // every thread has read its merge inputs' positions ... (buf is rewritten next)
+            __syncthreads();   // every thread has read its merge inputs (buf is rewritten next)
 #pragma unroll
             for (int k = 0; k < C; ++k)
                 if (k < E && p0 + k < p1) buf[p0 + k] = out[k];
@@ -745,8 +763,8 @@ int merge_launch(const JobDev& jd, const uint32_t* sorder, const uint4* old_keys
                  hipStream_t s) {
     const int64_t n = jd.g.n;
     const int n0 = (int)og.n, m = (int)(n - og.n);
-    if (n > 1024 * 15 || m < 1 || !og.narrow) {
-        set_error("merge: the union must fit 15,360 windows and the old keys must be narrow");
+    if (n > kMergeMaxN || m < 1 || m > kMergeMaxM || !og.narrow) {
+        set_error("merge: at most 512 new windows, a union of at most 15,360, narrow old keys");
         return BOOST_E_INVALID;
     }
     MergeArgs ma;
@@ -754,14 +772,12 @@ int merge_launch(const JobDev& jd, const uint32_t* sorder, const uint4* old_keys
     ma.og = og;
     ma.l0 = l0; ma.lm = lm; ma.n0 = n0; ma.m = m;
     ma.ib = n <= 1 ? 1 : 32 - __builtin_clz((unsigned)(n - 1));
-    const int cb = m <= 1024 ? 1 : m <= 3 * 1024 ? 3 : m <= 7 * 1024 ? 7 : 15;
+    const int c = n <= 1024 * 11 ? 11 : 15;
     auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
-    ma.rb_off = (int)a16((size_t)1024 * 15 * 4);
-    ma.x_off = (int)a16((size_t)ma.rb_off + (size_t)1024 * cb * 4);
-    size_t xbytes = (size_t)n0 * 4 > sizeof(CntScratch<1024>) ? (size_t)n0 * 4 : sizeof(CntScratch<1024>);
-    const size_t lds = (size_t)ma.x_off + a16(xbytes);
-    const void* k = cb == 1 ? (const void*)k_merge<1> : cb == 3 ? (const void*)k_merge<3>
-                  : cb == 7 ? (const void*)k_merge<7> : (const void*)k_merge<15>;
+    ma.rb_off = (int)a16((size_t)1024 * c * 4);
+    ma.x_off = (int)a16((size_t)ma.rb_off + (size_t)kMergeMaxM * 4);
+    const size_t lds = (size_t)ma.x_off + a16((size_t)n0 * 4);
+    const void* k = c == 11 ? (const void*)k_merge<11> : (const void*)k_merge<15>;
     VJB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     VJB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 1024, lds));
@@ -773,7 +789,8 @@ int merge_launch(const JobDev& jd, const uint32_t* sorder, const uint4* old_keys
     if (grid > jd.F) grid = jd.F;
     if (grid > kMaxSortGrid) grid = kMaxSortGrid;
     JobDev a = jd;
-    void* args[] = {(void*)&a, (void*)&sorder, (void*)&ma};
+    const uint32_t* ftab = jd.ftab;
+    void* args[] = {(void*)&a, (void*)&ftab, (void*)&sorder, (void*)&ma};
     VJB_HIP(hipLaunchKernel(k, dim3((unsigned)grid), dim3(1024), args, lds, s));
     return BOOST_OK;
 }

@@ -38,7 +38,11 @@ struct JobHost {
 // A prepared job that a new job extends: the new job's windows are the old
 // job's (in its caller order) followed by the new ones.
 struct ExtendSrc { const JobDev* old; int64_t l0; };
-constexpr int64_t kMergeMaxN = 1024 * 15;   // unions up to this size merge the old keys; larger ones are sorted
+// A union of at most kMergeMaxN windows that adds at most kMergeMaxM merges
+// the old keys with the sorted new windows; any other is sorted in full
+// (faster there: the merge still evaluates every window).
+constexpr int64_t kMergeMaxN = 1024 * 15;
+constexpr int64_t kMergeMaxM = 512;
 int check_job_args(int64_t n, const boost_feature_set* fs, const boost_options* o);
 size_t job_bytes(int64_t n, const boost_feature_set* fs);
 // ext == NULL: a job of d_images / d_labels (n windows).  Otherwise the union

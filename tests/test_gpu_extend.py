@@ -55,7 +55,7 @@ def _same(ext, fresh, all_values=True):
     assert np.array_equal(ext.weights().cpu().numpy(), fresh.weights().cpu().numpy())
 
 
-@pytest.mark.parametrize("frac", [0.01, 0.1, 0.5])
+@pytest.mark.parametrize("frac", [0.01, 0.1, 0.256, 0.257, 0.5])
 @pytest.mark.parametrize("precision", ["fp32_kahan", "fp32_wide"])
 def test_extend_equals_fresh(frac, precision):
     n0 = 2000
@@ -66,7 +66,7 @@ def test_extend_equals_fresh(frac, precision):
     base = _tr(old_img, old_lab, precision=precision)
     base.train(3)                      # a base that has trained: extension starts over on the union
     ext = base.extend(new_img, new_lab)
-    assert ext.merged()
+    assert ext.merged() == (m <= 512)  # larger additions are sorted in full
     fresh = _tr(np.concatenate([old_img, new_img]), np.concatenate([old_lab, new_lab]), precision=precision)
     _same(ext, fresh)
     for t in (base, ext, fresh):
@@ -98,14 +98,16 @@ def test_extend_edge_cases(case):
 
 
 def test_extend_headline_size_and_the_full_sort_beyond_the_merge_range():
-    """24x24 windows at the benchmark's scale: 10,000 + 5,000 (merged), and
+    """24x24 windows at the benchmark's scale: 14,500 + 500 (merged, 15 window
+    slots a thread), 10,000 + 5,000 (sorted in full: more than 512 new), and
     15,000 + 500 (beyond 15,360 windows: sorted in full); sorted keys and
     trajectories equal a fresh init."""
     images, labels = synth.workload_jobs("faces15k")[0].make()
     p = np.random.default_rng(957).permutation(len(labels))
     images, labels = np.ascontiguousarray(images[p]), np.ascontiguousarray(labels[p])
     extra_img, extra_lab = _data((958,), 200, 300, 24)
-    for n0, new_img, new_lab, merged in ((10000, images[10000:], labels[10000:], True),
+    for n0, new_img, new_lab, merged in ((14500, images[14500:], labels[14500:], True),
+                                        (10000, images[10000:], labels[10000:], False),
                                         (15000, extra_img, extra_lab, False)):
         old_img, old_lab = (images[:n0], labels[:n0]) if n0 < 15000 else (images, labels)
         say(f"extend 24x24: {n0} + {len(new_lab)}")
