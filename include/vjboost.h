@@ -73,9 +73,13 @@ typedef struct {
 /* ------------------------------------------------------------ options
  * precision: arithmetic of the per-round weighted-error scan.
  *   BOOST_PREC_FP32        FP32 weights, FP32 running sums (plain).
- *   BOOST_PREC_FP32_KAHAN  FP32 weights, FP32 running sums with two-sum
- *                          compensation; candidates (the compensated
- *                          prefix s + c) are compared in FP64.
+ *   BOOST_PREC_FP32_KAHAN  FP32 weights, a compensated FP32 running sum:
+ *                          Fast2Sum (the sum is biased so that it always
+ *                          dominates the added weight) collects each
+ *                          addition's exact rounding error in an FP32
+ *                          compensation term, folded back into the sum every
+ *                          16 keys; candidates (the prefix s + c) are
+ *                          compared in FP64.
  *   BOOST_PREC_FP64        FP64 weights and FP64 running sums (n <= 20000:
  *                          the table must fit in LDS).
  *   BOOST_PREC_FP32_WIDE   FP32 weights accumulated in FP64.  For weights
@@ -91,13 +95,16 @@ typedef struct {
  * eps_floor: > 0 and < 0.5 (default 1e-10).
  * schedule_id: 0 picks the default launch shape (512-thread workgroups, 8
  *   key units per load batch, 16 lanes per feature); 1 .. count-1 select
- *   other shapes (see boost_schedule_count), among them 9, which keeps 4
- *   key units per lane in flight all the time (rotating loads, the fastest
- *   single-job scan measured); BOOST_SCHEDULE_AUTO lets init
- *   time every shape that shares the default's 16-lane key layout on the
- *   job's own keys and keep the fastest (batches: per key format, then also
- *   the work-queue granularity).  Choices are cached per process by workload
- *   shape; boost_get_schedule / boost_batch_get_schedule report them.
+ *   other shapes (see boost_schedule_count), among them 9 and 10, which keep
+ *   4 key units per lane in flight all the time (rotating loads at 512 and
+ *   1024 threads); BOOST_SCHEDULE_AUTO lets init time every shape that
+ *   shares the default's 16-lane key layout on the job's own keys and keep
+ *   the fastest (batches: per key format, by successive halving, then also
+ *   the work-queue granularity).  Choices are cached per process by device
+ *   and workload shape, and also in the file named by the environment
+ *   variable VJBOOST_TUNE_CACHE when it is set (read on the first miss,
+ *   appended on each new choice; entries that do not fit are re-tuned);
+ *   boost_get_schedule / boost_batch_get_schedule report them.
  * flags: BOOST_FLAG_TIMING records per-kernel device times (boost_get_timing);
  *   BOOST_FLAG_NO_GRAPH launches kernels directly instead of replaying a
  *   captured HIP graph in boost_train. */
@@ -169,7 +176,9 @@ size_t boost_workspace_bytes(int64_t n, const boost_feature_set *fs, const boost
 /* Number of launch schedules (schedule_id values 0 .. count-1) for a precision. */
 int boost_schedule_count(int32_t precision);
 
-/* Forgets every BOOST_SCHEDULE_AUTO choice cached in this process. */
+/* Forgets every BOOST_SCHEDULE_AUTO choice cached in this process's memory
+ * (a VJBOOST_TUNE_CACHE file is left as it is and read again on the next
+ * miss). */
 void boost_tune_cache_clear(void);
 
 /* ------------------------------------------------------------ training

@@ -3,17 +3,23 @@
 // keys (window index + end-of-run flag) in the lane-segment layout that the
 // per-round scan reads.  Feature values never reach HBM.
 //
-// One workgroup per feature at a time.  Each thread holds C values in
-// registers (window r = k * NT + t in slot k), packed with the window index as
-// ((v - vmin) << ib) | r in 32 bits, and the workgroup sorts them with a
-// stable least-significant-digit radix sort over the value bits only, 4 bits
-// per pass: windows with equal values keep index order, which is the (value,
-// index) order.  A pass ranks each item among the items of its wave and slot
-// with the same digit (ballots), counts items per (digit, slot, wave) in LDS,
-// scans the counts in that order, and scatters through one LDS buffer.
-// A feature whose value range does not fit beside the index in 32 bits
-// (possible only for n > 16384) is sorted as 64-bit pairs in a per-workgroup
-// global scratch buffer (bitonic network) instead.
+// k_sort_cnt (every job of up to 31,744 windows): one workgroup per feature
+// at a time, in a visiting order that keeps features reading the same
+// integral-image corner planes together on one XCD.  Each thread evaluates C
+// windows (slot k of thread t is window k * NT + t), the values are packed
+// with the window index as ((v - vmin) << ib) | i in 32 bits, and the
+// workgroup sorts them with stable least-significant-digit counting passes
+// over the value bits only, 4 bits per pass (per-thread packed digit
+// counters, DPP wave scans, one scatter through an LDS buffer per pass):
+// windows with equal values keep index order, which is the (value, index)
+// order.  A feature whose value range does not fit beside a 15-bit index is
+// listed for the 64-bit path.
+// k_sort (jobs of more than 31,744 windows, and the listed features): ranks
+// each item among the items of its wave and slot with the same digit
+// (ballots), or, when the words need 64 bits, a bitonic sort in a
+// per-workgroup global scratch buffer.
+// k_merge (boost_extend): the keys of a job extended by a few windows, from
+// the old job's order and the new windows' (see below).
 #include <limits.h>
 
 #include "launch.h"
