@@ -46,6 +46,22 @@ __device__ __forceinline__ uint32_t bitmask(uint32_t d, int b) {
     return (uint32_t)(((int32_t)(d << (31 - b))) >> 31);
 }
 
+// v_max_f64 / v_min_f64 of a value and a candidate that may be a quiet NaN
+// (never a signalling one): in the hardware's IEEE mode the result is then
+// the other operand (IEEE-754 maxNum / minNum).  Issued directly because
+// the compiler, not knowing that an integer-masked value is not a
+// signalling NaN, would otherwise first quiet it with an extra max.
+__device__ __forceinline__ double max_qnan(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double min_qnan(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 template <int PREC> struct ScanTypes;
 template <> struct ScanTypes<BOOST_PREC_FP32>       { using W = float;  using A = float;  };
 template <> struct ScanTypes<BOOST_PREC_FP32_KAHAN> { using W = float;  using A = double; };
@@ -105,6 +121,30 @@ template <> struct LaneAcc<BOOST_PREC_FP32_KAHAN> {
         const double v = (double)t + (double)__uint_as_float(__float_as_uint(c) | m);
         mx = fmax(mx, v);
         mn = fmin(mn, v);
+    }
+    // Two consecutive keys.  The second key's candidate is s + c as above;
+    // the first key's is derived from it as v1 - w1 (FP64): t0 + c0 and
+    // t1 + c1 differ by w1 up to the rounding of the compensation sum
+    // (at most 2^-24 |c|), and the FP64 subtraction rounds by at most
+    // 2^-53 * 4.  Each candidate is masked by an integer OR of the
+    // all-ones pattern into its high word (a quiet NaN).  Per pair this
+    // takes one convert and one FP64 operation fewer than two key() calls.
+    __device__ __forceinline__ void pair(float w0, uint32_t m0, float w1, uint32_t m1) {
+        const float t0 = s + w0;
+        const float z0 = t0 - s;    // exact: |s| >= |w0|
+        const float e0 = w0 - z0;
+        const float t1 = t0 + w1;
+        const float z1 = t1 - t0;   // exact: |t0| >= |w1|
+        const float e1 = w1 - z1;
+        s = t1;
+        c = (c + e0) + e1;
+        const double v1 = (double)t1 + (double)c;
+        const double v0 = v1 - (double)w1;
+        // mask: the all-ones pattern in the high word makes a quiet NaN
+        const double c1v = __longlong_as_double(__double_as_longlong(v1) | (long long)((uint64_t)m1 << 32));
+        const double c0v = __longlong_as_double(__double_as_longlong(v0) | (long long)((uint64_t)m0 << 32));
+        mx = max_qnan(max_qnan(mx, c0v), c1v);
+        mn = min_qnan(min_qnan(mn, c0v), c1v);
     }
     __device__ __forceinline__ void unit_end() {
         const float t = s + c;
@@ -178,8 +218,12 @@ __device__ __forceinline__ void scan_dword(LaneAcc<PREC>& a, const typename Scan
     using Wt = typename ScanTypes<PREC>::W;
     const Wt w0 = tab_lo<Wt, NARROW>(tab, d);
     const Wt w1 = tab_hi<Wt, NARROW>(tab, d);
-    a.key(w0, nosplit_lo<NARROW>(d));
-    a.key(w1, nosplit_hi<NARROW>(d));
+    if constexpr (PREC == BOOST_PREC_FP32_KAHAN) {
+        a.pair(w0, nosplit_lo<NARROW>(d), w1, nosplit_hi<NARROW>(d));
+    } else {
+        a.key(w0, nosplit_lo<NARROW>(d));
+        a.key(w1, nosplit_hi<NARROW>(d));
+    }
 }
 
 // One unit (8 keys).  The compensated mode folds its correction back into
