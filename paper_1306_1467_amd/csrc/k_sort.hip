@@ -316,6 +316,22 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
     v = dpp_add<0x143, 0xC, false>(v);   // row_bcast:31 into rows 2 and 3
     return v;
 }
+// Eight independent inclusive scans, step by step, so that each DPP read
+// has seven other adds between it and the write it depends on.
+__device__ __forceinline__ void wave_scan_incl8(const uint32_t* f, uint32_t* v) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) v[p] = dpp_add<0x111, 0xF, true>(f[p]);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) v[p] = dpp_add<0x112, 0xF, true>(v[p]);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) v[p] = dpp_add<0x114, 0xF, true>(v[p]);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) v[p] = dpp_add<0x118, 0xF, true>(v[p]);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) v[p] = dpp_add<0x142, 0xA, false>(v[p]);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) v[p] = dpp_add<0x143, 0xC, false>(v[p]);
+}
 
 // Maximum and minimum of a 32-bit signed value over the 64 lanes of a wave
 // (DPP row shifts and broadcasts; a lane a shift or broadcast does not reach
@@ -337,14 +353,15 @@ __device__ __forceinline__ int32_t wave_ext(int32_t v) {
 }
 
 // Values of windows k NT + threadIdx.x, k < C (0 past n), the feature type
-// fixed at compile time so the loads of all slots issue together.
-template <int TYPE, int NT, int C>
+// fixed at compile time so the loads of all slots issue together.  The
+// caller guarantees n >= K0 NT: the first K0 slots need no bound check.
+template <int TYPE, int NT, int C, int K0>
 __device__ __forceinline__ void eval_windows(const int32_t* __restrict__ ii, int64_t S, int wp1, int x, int y, int cw,
                                              int ch, int n, int32_t* v) {
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const int i = k * NT + threadIdx.x;
-        v[k] = i < n ? haar_value_t<TYPE>(ii, S, wp1, x, y, cw, ch, i) : 0;
+        v[k] = (k < K0 || i < n) ? haar_value_t<TYPE>(ii, S, wp1, x, y, cw, ch, i) : 0;
     }
 }
 
@@ -352,18 +369,18 @@ __device__ __forceinline__ void eval_windows(const int32_t* __restrict__ ii, int
 template <int NT>
 struct CntScratch {
     uint16_t tab[16 * NT];         // tab[d * NT + t]: thread t's start offset of digit d
-    uint32_t wtot[NT / 64][8];     // per wave: the digit totals, digits 2p, 2p + 1 in word p
+    alignas(16) uint32_t wtot[NT / 64][8];   // per wave: the digit totals, digits 2p, 2p + 1 in word p
     alignas(16) uint16_t base[NT / 64][16];   // per wave: where each digit's run of this wave starts
 };
 
 // Stable LSD counting-sort passes (4-bit digits) over bits [sh0, sh1) of
 // the NT * C words it[] (thread t holds positions t C .. t C + C - 1 of the
 // current order).  Each pass scatters into buf (NT * C words) and reloads;
-// on return it[] and buf hold the sorted order (buf untouched when no pass
-// runs).  The caller must have finished reading buf (a barrier) before the
-// call; the call ends with buf complete (after a barrier).  A thread counts
-// its items' digits in groups of at most 15 items (16 4-bit fields per
-// group).
+// on return buf holds the sorted order (untouched when no pass runs; it[] is
+// not reloaded after the last pass).  The caller must have finished reading
+// buf (a barrier) before the call; when a pass runs, the call ends with buf
+// complete (after a barrier).  A thread counts its items' digits in groups
+// of at most 15 items (16 4-bit fields per group).
 template <int NT, int C>
 __device__ __forceinline__ void cnt_sort_passes(uint32_t* it, uint32_t* buf, CntScratch<NT>& cs, int sh0, int sh1) {
     static_assert(C <= 31 && (C & 1) == 1, "at most 31 items a thread; odd C keeps the chunk reads conflict-free");
@@ -378,8 +395,10 @@ __device__ __forceinline__ void cnt_sort_passes(uint32_t* it, uint32_t* buf, Cnt
         for (int g = 0; g < NG; ++g) cnt[g] = 0;
 #pragma unroll
         for (int k = 0; k < C; ++k) cnt[k / 15] += 1ull << (4 * ((it[k] >> sh) & 15u));
-        // 2. scan across the wave (digits 2p, 2p + 1 in word p), then across (digit, wave)
-        uint32_t ex[8];
+        // 2. scan across the wave (digits 2p, 2p + 1 in word p; the eight
+        // scans are independent, so their steps interleave), then across
+        // (digit, wave)
+        uint32_t ex[8], inc[8];
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
             uint32_t f = 0;
@@ -388,9 +407,15 @@ __device__ __forceinline__ void cnt_sort_passes(uint32_t* it, uint32_t* buf, Cnt
                 const uint32_t c2 = (uint32_t)(cnt[g] >> (8 * p));
                 f += (c2 & 0xFu) | ((c2 & 0xF0u) << 12);
             }
-            const uint32_t inc = wave_scan_incl(f);
-            ex[p] = inc - f;
-            if (lane == 63) cs.wtot[wv][p] = inc;
+            ex[p] = f;
+        }
+        wave_scan_incl8(ex, inc);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) ex[p] = inc[p] - ex[p];
+        if (lane == 63) {
+            uint4* wt = reinterpret_cast<uint4*>(&cs.wtot[wv][0]);
+            wt[0] = make_uint4(inc[0], inc[1], inc[2], inc[3]);
+            wt[1] = make_uint4(inc[4], inc[5], inc[6], inc[7]);
         }
         __syncthreads();   // also: every thread has read its chunk of the previous order
         if (wv == 0) {
@@ -436,10 +461,11 @@ __device__ __forceinline__ void cnt_sort_passes(uint32_t* it, uint32_t* buf, Cnt
             buf[cs.tab[d * NT + tid] + r] = it[k];
         }
         __syncthreads();
+        if (C > 15 || sh + 4 < sh1) {   // (kept for the 31-slot kernel: it spills less so)
 #pragma unroll
-        for (int k = 0; k < C; ++k) it[k] = buf[tid * C + k];
+            for (int k = 0; k < C; ++k) it[k] = buf[tid * C + k];
+        }
     }
-    __syncthreads();
 }
 
 // Values of windows k NT + threadIdx.x (k < C, below n) of a feature of type
@@ -464,17 +490,17 @@ __device__ __forceinline__ void eval_windows_lds(const int32_t* __restrict__ ii,
 
 // Values of feature `desc` on windows k NT + threadIdx.x, k < C: the loads
 // are issued here and waited for where the values are first used.
-template <int NT, int C>
+template <int NT, int C, int K0 = 0>
 __device__ __forceinline__ void eval_values(const JobDev& jd, uint32_t desc, int n, int32_t* v) {
     const int wp1 = jd.W + 1;
     int t, x, y, cw, ch;
     unpack_feature(desc, t, x, y, cw, ch);
     switch (t) {
-    case BOOST_TYPE_3H: eval_windows<BOOST_TYPE_3H, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
-    case BOOST_TYPE_3V: eval_windows<BOOST_TYPE_3V, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
-    case BOOST_TYPE_2H: eval_windows<BOOST_TYPE_2H, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
-    case BOOST_TYPE_2V: eval_windows<BOOST_TYPE_2V, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
-    default: eval_windows<BOOST_TYPE_4, NT, C>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
+    case BOOST_TYPE_3H: eval_windows<BOOST_TYPE_3H, NT, C, K0>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
+    case BOOST_TYPE_3V: eval_windows<BOOST_TYPE_3V, NT, C, K0>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
+    case BOOST_TYPE_2H: eval_windows<BOOST_TYPE_2H, NT, C, K0>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
+    case BOOST_TYPE_2V: eval_windows<BOOST_TYPE_2V, NT, C, K0>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
+    default: eval_windows<BOOST_TYPE_4, NT, C, K0>(jd.ii, jd.ii_stride, wp1, x, y, cw, ch, n, v); break;
     }
 }
 
@@ -511,8 +537,8 @@ __device__ __forceinline__ void eval_to_lds(const JobDev& jd, uint32_t desc, int
 }
 
 // The range of the values over the first n windows (every thread gets the
-// same; one barrier).
-template <int NT, int C>
+// same; one barrier).  n >= K0 NT as for eval_windows.
+template <int NT, int C, int K0 = 0>
 __device__ __forceinline__ void value_range(const int32_t* v, int n, int32_t* rmin, int32_t* rmax, int32_t& vmin,
                                             int32_t& vmax) {
     constexpr int NW = NT / 64;
@@ -522,7 +548,7 @@ __device__ __forceinline__ void value_range(const int32_t* v, int n, int32_t* rm
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const int i = k * NT + tid;
-        if (i < n) {
+        if (k < K0 || i < n) {
             vmin = v[k] < vmin ? v[k] : vmin;
             vmax = v[k] > vmax ? v[k] : vmax;
         }
@@ -567,7 +593,7 @@ struct SortCntLds {
 // a feature whose packed words would need more than 32 bits is not sorted
 // here; its index goes to defer[16 + c] with c = atomicAdd(defer, 1), for
 // the 64-bit path (k_sort over that list).
-template <int NT, int C>
+template <int NT, int C, int K0>
 __global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, const uint32_t* __restrict__ ftab,
                                                  const uint32_t* __restrict__ sorder, int ib,
                                                  uint32_t* __restrict__ defer) {
@@ -581,14 +607,10 @@ __global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, const uint32_t* __re
         // values: in registers (up to 15 a thread), else through LDS
         int32_t vmin, vmax;
         int32_t v[C <= 15 ? C : 1];
-#ifndef VJB_EXP_LDSEVAL
         constexpr bool kRegs = C <= 15;
-#else
-        constexpr bool kRegs = false;
-#endif
         if constexpr (kRegs) {
-            eval_values<NT, C>(jd, ftab[j], n, v);
-            value_range<NT, C>(v, n, L.rmin, L.rmax, vmin, vmax);
+            eval_values<NT, C, K0>(jd, ftab[j], n, v);
+            value_range<NT, C, K0>(v, n, L.rmin, L.rmax, vmin, vmax);
         } else {
             eval_to_lds<NT, C>(jd, ftab[j], n, L.buf, L.rmin, L.rmax, vmin, vmax);
         }
@@ -607,7 +629,7 @@ __global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, const uint32_t* __re
 #pragma unroll
             for (int k = 0; k < C; ++k) {
                 const int i = k * NT + tid;
-                L.buf[i] = i < n ? (((uint32_t)(v[k] - vmin)) << ib) | (uint32_t)i : 0xFFFFFFFFu;
+                L.buf[i] = (k < K0 || i < n) ? (((uint32_t)(v[k] - vmin)) << ib) | (uint32_t)i : 0xFFFFFFFFu;
             }
             __syncthreads();
 #pragma unroll
@@ -631,7 +653,10 @@ __global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, const uint32_t* __re
             unit_keys_w32<NT, 1>(jd.g, L.buf, ib, (1u << ib) - 1u, &kq, k * NT);
             store_unit_keys<NT, 1>(jd, j, &kq, k * NT);
         }
-        __syncthreads();
+        // the next feature overwrites buf: with values in registers only after
+        // the barrier of its value range, which every thread reaches after
+        // its key reads here; with values through LDS, during its evaluation
+        if constexpr (!kRegs) __syncthreads();
     }
 }
 
@@ -801,12 +826,17 @@ int merge_launch(const JobDev& jd, const uint32_t* sorder, const uint4* old_keys
     return BOOST_OK;
 }
 
-template <int NT, int C>
+// K0: slots every thread holds a window in (n >= K0 NT).
+template <int NT, int C, int K0>
 static int sort_cnt_launch(const JobDev& jd, const uint32_t* sorder, uint32_t* defer, int num_cu, hipStream_t s) {
     const int64_t n = jd.g.n;
+    if (n < (int64_t)K0 * NT || n > (int64_t)C * NT) {
+        set_error("sort: window count outside the kernel's range");
+        return BOOST_E_INVALID;
+    }
     int ib = n <= 1 ? 1 : 32 - __builtin_clz((unsigned)(n - 1));
     const size_t lds = sizeof(SortCntLds<NT, C>);
-    const void* k = (const void*)k_sort_cnt<NT, C>;
+    const void* k = (const void*)k_sort_cnt<NT, C, K0>;
     VJB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     VJB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, NT, lds));
@@ -856,12 +886,13 @@ static int sort_launch_c(const JobDev& jd, uint64_t* scratch, const uint32_t* li
 int sort_launch(const JobDev& jd, const uint32_t* sorder, uint64_t* scratch, uint32_t* defer, int num_cu,
                 hipStream_t s) {
     const int64_t n = jd.g.n;
-    if (n <= 256 * 7) return sort_cnt_launch<256, 7>(jd, sorder, nullptr, num_cu, s);
-    if (n <= 512 * 7) return sort_cnt_launch<512, 7>(jd, sorder, nullptr, num_cu, s);
-    if (n <= 1024 * 7) return sort_cnt_launch<1024, 7>(jd, sorder, nullptr, num_cu, s);
-    if (n <= 1024 * 11) return sort_cnt_launch<1024, 11>(jd, sorder, nullptr, num_cu, s);
-    if (n <= 1024 * 15) return sort_cnt_launch<1024, 15>(jd, sorder, nullptr, num_cu, s);
-    if (n <= kNarrowMaxN + 1) return sort_cnt_launch<1024, 31>(jd, sorder, nullptr, num_cu, s);   // 14-bit indices
+    // each tier's K0: the slots the previous tier's bound already fills
+    if (n <= 256 * 7) return sort_cnt_launch<256, 7, 0>(jd, sorder, nullptr, num_cu, s);
+    if (n <= 512 * 7) return sort_cnt_launch<512, 7, 3>(jd, sorder, nullptr, num_cu, s);
+    if (n <= 1024 * 7) return sort_cnt_launch<1024, 7, 3>(jd, sorder, nullptr, num_cu, s);
+    if (n <= 1024 * 11) return sort_cnt_launch<1024, 11, 7>(jd, sorder, nullptr, num_cu, s);
+    if (n <= 1024 * 15) return sort_cnt_launch<1024, 15, 11>(jd, sorder, nullptr, num_cu, s);
+    if (n <= kNarrowMaxN + 1) return sort_cnt_launch<1024, 31, 15>(jd, sorder, nullptr, num_cu, s);   // 14-bit indices
     if (n <= 1024 * 31) {
         // 15-bit indices: features whose values span more than 17 bits go
         // through the 64-bit path, listed by the counting sort
@@ -870,7 +901,7 @@ int sort_launch(const JobDev& jd, const uint32_t* sorder, uint64_t* scratch, uin
             return BOOST_E_INVALID;
         }
         VJB_HIP(hipMemsetAsync(defer, 0, 4, s));
-        int rc = sort_cnt_launch<1024, 31>(jd, sorder, defer, num_cu, s);
+        int rc = sort_cnt_launch<1024, 31, 15>(jd, sorder, defer, num_cu, s);
         if (rc != BOOST_OK) return rc;
         return sort_launch_c<512, 64>(jd, scratch, defer, num_cu, s);
     }
