@@ -103,48 +103,44 @@ template <> struct LaneAcc<BOOST_PREC_FP32> {
 // 2^-45.  A candidate is s + c evaluated in FP64
 // (exact for two floats of these magnitudes); rounding it to FP32 would cost
 // 2^-24 of the prefix, more than a 1e-6 relative error once the minimal
-// error is below a few percent.  The split mask is applied to c before its
-// conversion (an integer OR with the all-ones pattern gives a quiet NaN,
-// which the conversion and the FP64 addition carry through), so masking
-// costs one FP32 operation.
+// error is below a few percent.
 constexpr float kKahanBias = 2.0f;
 
 template <> struct LaneAcc<BOOST_PREC_FP32_KAHAN> {
     float s = kKahanBias, c = 0.f;
     double mx = (double)kKahanBias - 4.0, mn = (double)kKahanBias + 4.0;
-    __device__ __forceinline__ void key(float w, uint32_t m) {
-        const float t = s + w;
-        const float z = t - s;      // exact: |s| >= |w|
-        const float e = w - z;      // exact: the rounding error of s + w
-        s = t;
-        c += e;
-        const double v = (double)t + (double)__uint_as_float(__float_as_uint(c) | m);
-        mx = fmax(mx, v);
-        mn = fmin(mn, v);
-    }
-    // Two consecutive keys.  The second key's candidate is s + c as above;
-    // the first key's is derived from it as v1 - w1 (FP64): t0 + c0 and
-    // t1 + c1 differ by w1 up to the rounding of the compensation sum
-    // (at most 2^-24 |c|), and the FP64 subtraction rounds by at most
-    // 2^-53 * 4.  Each candidate is masked by an integer OR of the
-    // all-ones pattern into its high word (a quiet NaN).  Per pair this
-    // takes one convert and one FP64 operation fewer than two key() calls.
-    __device__ __forceinline__ void pair(float w0, uint32_t m0, float w1, uint32_t m1) {
-        const float t0 = s + w0;
-        const float z0 = t0 - s;    // exact: |s| >= |w0|
-        const float e0 = w0 - z0;
-        const float t1 = t0 + w1;
-        const float z1 = t1 - t0;   // exact: |t0| >= |w1|
-        const float e1 = w1 - z1;
-        s = t1;
-        c = (c + e0) + e1;
-        const double v1 = (double)t1 + (double)c;
-        const double v0 = v1 - (double)w1;
-        // mask: the all-ones pattern in the high word makes a quiet NaN
-        const double c1v = __longlong_as_double(__double_as_longlong(v1) | (long long)((uint64_t)m1 << 32));
-        const double c0v = __longlong_as_double(__double_as_longlong(v0) | (long long)((uint64_t)m0 << 32));
-        mx = max_qnan(max_qnan(mx, c0v), c1v);
-        mn = min_qnan(min_qnan(mn, c0v), c1v);
+    // One unit of eight keys.  s and c step through the eight weights
+    // (Fast2Sum for s, the errors added to c in key order).  Only the last
+    // key's candidate is formed from s + c; each earlier key's is the next
+    // one's minus the next key's weight, in FP64.  The compensated sums
+    // after keys k and k + 1 differ by w_{k+1} up to the rounding of one
+    // addition to c (at most 2^-24 |c|), and each FP64 subtraction rounds by
+    // at most 2^-53 * 4, so every candidate stays within about 1e-12 of the
+    // compensated sum at its key.  That is one convert and one FP64
+    // operation per key, plus two per unit.  Each candidate is masked by an
+    // integer OR of the all-ones pattern into its high word (a quiet NaN,
+    // which the maximum and minimum skip).
+    __device__ __forceinline__ void unit8(const float* w, const uint32_t* m) {
+        float e[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float t = s + w[k];
+            const float z = t - s;  // exact: |s| >= |w|
+            e[k] = w[k] - z;        // exact: the rounding error of s + w
+            s = t;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c += e[k];
+        double v[8];
+        v[7] = (double)s + (double)c;
+#pragma unroll
+        for (int k = 7; k > 0; --k) v[k - 1] = v[k] - (double)w[k];
+#pragma unroll
+        for (int k = 7; k >= 0; --k) {
+            const double cv = __longlong_as_double(__double_as_longlong(v[k]) | (long long)((uint64_t)m[k] << 32));
+            mx = max_qnan(mx, cv);
+            mn = min_qnan(mn, cv);
+        }
     }
     __device__ __forceinline__ void unit_end() {
         const float t = s + c;
@@ -216,14 +212,8 @@ __device__ __forceinline__ uint32_t nosplit_hi(uint32_t d) { return NARROW ? bit
 template <int PREC, bool NARROW>
 __device__ __forceinline__ void scan_dword(LaneAcc<PREC>& a, const typename ScanTypes<PREC>::W* tab, uint32_t d) {
     using Wt = typename ScanTypes<PREC>::W;
-    const Wt w0 = tab_lo<Wt, NARROW>(tab, d);
-    const Wt w1 = tab_hi<Wt, NARROW>(tab, d);
-    if constexpr (PREC == BOOST_PREC_FP32_KAHAN) {
-        a.pair(w0, nosplit_lo<NARROW>(d), w1, nosplit_hi<NARROW>(d));
-    } else {
-        a.key(w0, nosplit_lo<NARROW>(d));
-        a.key(w1, nosplit_hi<NARROW>(d));
-    }
+    a.key(tab_lo<Wt, NARROW>(tab, d), nosplit_lo<NARROW>(d));
+    a.key(tab_hi<Wt, NARROW>(tab, d), nosplit_hi<NARROW>(d));
 }
 
 // One unit (8 keys).  The compensated mode folds its correction back into
@@ -234,10 +224,24 @@ __device__ __forceinline__ void scan_dword(LaneAcc<PREC>& a, const typename Scan
 template <int PREC, bool NARROW>
 __device__ __forceinline__ void scan_unit(LaneAcc<PREC>& a, const typename ScanTypes<PREC>::W* tab, const uint4& u,
                                           bool odd) {
-    scan_dword<PREC, NARROW>(a, tab, u.x);
-    scan_dword<PREC, NARROW>(a, tab, u.y);
-    scan_dword<PREC, NARROW>(a, tab, u.z);
-    scan_dword<PREC, NARROW>(a, tab, u.w);
+    if constexpr (PREC == BOOST_PREC_FP32_KAHAN) {
+        const uint32_t d[4] = {u.x, u.y, u.z, u.w};
+        float w[8];
+        uint32_t m[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            w[2 * q] = tab_lo<float, NARROW>(tab, d[q]);
+            w[2 * q + 1] = tab_hi<float, NARROW>(tab, d[q]);
+            m[2 * q] = nosplit_lo<NARROW>(d[q]);
+            m[2 * q + 1] = nosplit_hi<NARROW>(d[q]);
+        }
+        a.unit8(w, m);
+    } else {
+        scan_dword<PREC, NARROW>(a, tab, u.x);
+        scan_dword<PREC, NARROW>(a, tab, u.y);
+        scan_dword<PREC, NARROW>(a, tab, u.z);
+        scan_dword<PREC, NARROW>(a, tab, u.w);
+    }
     if (odd) a.unit_end();
 }
 
