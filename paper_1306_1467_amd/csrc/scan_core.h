@@ -119,27 +119,28 @@ template <> struct LaneAcc<BOOST_PREC_FP32_KAHAN> {
     // compensated sum at its key.  That is one convert and one FP64
     // operation per key, plus two per unit.  Each candidate is masked by an
     // integer OR of the all-ones pattern into its high word (a quiet NaN,
-    // which the maximum and minimum skip).
-    __device__ __forceinline__ void unit8(const float* w, const uint32_t* m) {
-        float e[8];
+    // which the maximum and minimum skip); the pattern is taken from the
+    // key's run-end bit (bit 0 of its dword for the low key, bit 1 or 16 for
+    // the high one) where it is used, to keep few registers live.
+    template <bool NARROW>
+    __device__ __forceinline__ void unit8(const float* w, const uint32_t* d) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const float t = s + w[k];
             const float z = t - s;  // exact: |s| >= |w|
-            e[k] = w[k] - z;        // exact: the rounding error of s + w
+            c += w[k] - z;          // w - z is exact: the rounding error of s + w
             s = t;
         }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) c += e[k];
-        double v[8];
-        v[7] = (double)s + (double)c;
-#pragma unroll
-        for (int k = 7; k > 0; --k) v[k - 1] = v[k] - (double)w[k];
+        double v = (double)s + (double)c;
 #pragma unroll
         for (int k = 7; k >= 0; --k) {
-            const double cv = __longlong_as_double(__double_as_longlong(v[k]) | (long long)((uint64_t)m[k] << 32));
+            // the next candidate first: the mask then overwrites v's high word in place
+            const double vn = k > 0 ? v - (double)w[k] : 0.0;
+            const uint32_t m = bitmask(d[k >> 1], (k & 1) ? (NARROW ? 1 : 16) : 0);
+            const double cv = __longlong_as_double(__double_as_longlong(v) | (long long)((uint64_t)m << 32));
             mx = max_qnan(mx, cv);
             mn = min_qnan(mn, cv);
+            v = vn;
         }
     }
     __device__ __forceinline__ void unit_end() {
@@ -227,15 +228,12 @@ __device__ __forceinline__ void scan_unit(LaneAcc<PREC>& a, const typename ScanT
     if constexpr (PREC == BOOST_PREC_FP32_KAHAN) {
         const uint32_t d[4] = {u.x, u.y, u.z, u.w};
         float w[8];
-        uint32_t m[8];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             w[2 * q] = tab_lo<float, NARROW>(tab, d[q]);
             w[2 * q + 1] = tab_hi<float, NARROW>(tab, d[q]);
-            m[2 * q] = nosplit_lo<NARROW>(d[q]);
-            m[2 * q + 1] = nosplit_hi<NARROW>(d[q]);
         }
-        a.unit8(w, m);
+        a.template unit8<NARROW>(w, d);
     } else {
         scan_dword<PREC, NARROW>(a, tab, u.x);
         scan_dword<PREC, NARROW>(a, tab, u.y);
