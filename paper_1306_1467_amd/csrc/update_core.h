@@ -26,6 +26,7 @@ struct UpdLds {
     WgBest wb[kUpdWg / 64];
     double sh[kUpdWg / 64];
     Wt val[kMaxSeg * 8];       // table values of the winning lane's keys, rank order
+    uint16_t idx[kMaxSeg * 8];   // their window indices
     uint32_t flags[kMaxSeg];   // run-end flags, one byte per unit
     int64_t k;
     int32_t theta;
@@ -54,6 +55,17 @@ __device__ __forceinline__ void update_body(const JobDev& jd, const WgBest* __re
     __shared__ UpdLds<Wt> lds;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     JobState* st = jd.st;
+    // the round's state and this workgroup's own weights, loaded first: none
+    // of them depends on the stump
+    const int64_t n = jd.g.n;
+    const int64_t l = st->n_pos;
+    const double S = st->sum_w;
+    const double rS = 1.0 / S;
+    const int par = st->cur;   // the scan's weights; this kernel writes the other half
+    const double* w_in = weights(jd, par);
+    double* w_out = weights(jd, par ^ 1);
+    const int64_t i = (int64_t)part * kUpdWg + tid;
+    const double w_i = i < n ? w_in[i] : 0.0;
     // 1. argmin over the scan workgroups' candidates
     WgBest b{DBL_MAX, -1, 0, -1};
     for (int k = tid; k < n_wg; k += kUpdWg) {
@@ -84,18 +96,11 @@ __device__ __forceinline__ void update_body(const JobDev& jd, const WgBest* __re
         }
         return;
     }
-    const int64_t n = jd.g.n, j = b.feature;
+    const int64_t j = b.feature;
     const int pol = b.polarity;
     const uint32_t desc = jd.ftab[j];
     const int wp1 = jd.W + 1;
-    const int64_t l = st->n_pos;
-    const double S = st->sum_w;
-    const double rS = 1.0 / S;
-    const int par = st->cur;   // the scan's weights; this kernel writes the other half
-    const double* w_in = weights(jd, par);
-    double* w_out = weights(jd, par ^ 1);
     // this workgroup's windows: values are loaded while the split is found
-    const int64_t i = (int64_t)part * kUpdWg + tid;
     const int32_t f = i < n ? haar_value(jd.ii, jd.ii_stride, wp1, desc, i) : 0;
     // 2. split rank: the winning lane's segment (table values, run-end flags)
     // is staged in LDS by the whole workgroup; the lane's prefix at every key
@@ -119,6 +124,8 @@ __device__ __forceinline__ void update_body(const JobDev& jd, const WgBest* __re
             uint32_t i0, f0, i1, f1;
             decode_pair(jd.g.narrow, dw[h], i0, f0, i1, f1);
             fb |= (f0 << (2 * h)) | (f1 << (2 * h + 1));
+            lds.idx[u * 8 + 2 * h] = (uint16_t)i0;
+            lds.idx[u * 8 + 2 * h + 1] = (uint16_t)i1;
             lds.val[u * 8 + 2 * h] = i0 < (uint32_t)n ? table_value<PREC>(w_in[i0], rS, i0 < (uint32_t)l) : (Wt)0;
             lds.val[u * 8 + 2 * h + 1] = i1 < (uint32_t)n ? table_value<PREC>(w_in[i1], rS, i1 < (uint32_t)l) : (Wt)0;
         }
@@ -192,9 +199,12 @@ __device__ __forceinline__ void update_body(const JobDev& jd, const WgBest* __re
     }
     if (tid == 0) {
         // 3. threshold from the window at the rank just above (p = +1) or at
-        // (p = -1) the split
+        // (p = -1) the split; its index is in the staged segment unless the
+        // rank is the next lane's first
         const int64_t rk = pol > 0 ? (k < n ? k : n - 1) : (k > 0 ? k - 1 : 0);
-        const int32_t v = haar_value(jd.ii, jd.ii_stride, wp1, desc, index_at_rank(jd, j, rk));
+        const int64_t pos = L >= 0 ? rk - 8 * lane_start(jd.g, L) : -1;
+        const int32_t wi = pos >= 0 && pos < 8 * (int64_t)cntL ? (int32_t)lds.idx[pos] : index_at_rank(jd, j, rk);
+        const int32_t v = haar_value(jd.ii, jd.ii_stride, wp1, desc, wi);
         lds.k = k;
         lds.theta = pol > 0 ? (k < n ? v : v + 1) : (k > 0 ? v : v - 1);
     }
@@ -225,7 +235,7 @@ __device__ __forceinline__ void update_body(const JobDev& jd, const WgBest* __re
     if (i < n) {
         const int h = (int64_t)pol * f < (int64_t)pol * theta ? 1 : 0;
         const int y = i < l ? 1 : 0;
-        wn = w_in[i] * rS;
+        wn = w_i * rS;
         if (h == y) wn = wn * beta;
         w_out[i] = wn;
     }
