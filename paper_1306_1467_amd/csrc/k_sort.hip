@@ -667,7 +667,8 @@ __global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, const uint32_t* __re
 // the new windows are sorted, and the two ordered lists are merged.
 //   1. the union's values of the feature (one per window, as in k_sort_cnt)
 //      and its packed words in index order;
-//   2. the new windows' words, sorted by the counting-sort passes (m <= 1024 CB);
+//   2. the new windows' words in order (m <= 512), each ranked by counting
+//      the new words below it;
 //   3. the old windows' words in the old order (decoded from the old keys,
 //      each old index moved to its union index; the move keeps their order);
 //   4. a merge of the two lists (merge path: each thread finds where its E
@@ -681,13 +682,15 @@ struct MergeArgs {
     int32_t l0, lm, n0, m;   // old positives, new positives, old windows, new windows
     int32_t ib;              // index bits of the union
     int32_t rb_off, x_off;   // LDS byte offsets of the new words' buffer and of the shared region
+    int32_t nb_off;          // LDS byte offset of the new words in index order (16-byte aligned)
 };
 
 // C: window slots a thread holds (n <= 1024 C).  The new windows (m <= 512)
-// are put in order by counting: each new word's rank among the new words is
-// the number of new words below it (one comparison pass over the m words,
-// no barriers; the counting-sort passes cost more than this at such sizes,
-// and more than sorting the whole union once m passes about 512).
+// are put in order by counting: their words are gathered into one array, and
+// each new word's rank among them is the number of words below it (one pass
+// over the m words, four a read; the counting-sort passes cost more than
+// this at such sizes, and more than sorting the whole union once m passes
+// about 512).
 template <int C>
 __global__ __launch_bounds__(1024) void k_merge(JobDev jd, const uint32_t* __restrict__ ftab,
                                                const uint32_t* __restrict__ sorder, MergeArgs ma) {
@@ -728,12 +731,21 @@ __global__ __launch_bounds__(1024) void k_merge(JobDev jd, const uint32_t* __res
             if (i < n) buf[i] = (((uint32_t)(v[k] - vmin)) << ma.ib) | (uint32_t)i;
         }
         __syncthreads();
-        // 2. the new windows in order (union indices l0 .. l0 + lm - 1, then n - mn .. n - 1)
+        // 2. the new windows in order (union indices l0 .. l0 + lm - 1, then n - mn .. n - 1):
+        // gathered into nbuf, then each ranked against all of them, four words a read
         (void)rb;
+        uint32_t* nbuf = (uint32_t*)(smem + ma.nb_off);
+        if (tid < ma.m) nbuf[tid] = buf[new_index(tid)];
+        __syncthreads();
         if (tid < ma.m) {
-            const uint32_t x = buf[new_index(tid)];
+            const uint32_t x = nbuf[tid];
             int r = 0;
-            for (int q = 0; q < ma.m; ++q) r += buf[new_index(q)] < x ? 1 : 0;   // words are unique
+            const int m4 = ma.m & ~3;
+            for (int q = 0; q < m4; q += 4) {   // words are unique
+                const uint4 y = *reinterpret_cast<const uint4*>(nbuf + q);
+                r += (y.x < x ? 1 : 0) + (y.y < x ? 1 : 0) + (y.z < x ? 1 : 0) + (y.w < x ? 1 : 0);
+            }
+            for (int q = m4; q < ma.m; ++q) r += nbuf[q] < x ? 1 : 0;
             rbuf[r] = x;
         }
         // 3. the old windows in the old order
@@ -807,7 +819,8 @@ int merge_launch(const JobDev& jd, const uint32_t* sorder, const uint4* old_keys
     auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
     ma.rb_off = (int)a16((size_t)1024 * c * 4);
     ma.x_off = (int)a16((size_t)ma.rb_off + (size_t)kMergeMaxM * 4);
-    const size_t lds = (size_t)ma.x_off + a16((size_t)n0 * 4);
+    ma.nb_off = (int)a16((size_t)ma.x_off + (size_t)n0 * 4);
+    const size_t lds = (size_t)ma.nb_off + (size_t)kMergeMaxM * 4;
     const void* k = c == 11 ? (const void*)k_merge<11> : (const void*)k_merge<15>;
     VJB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
