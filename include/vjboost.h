@@ -209,10 +209,11 @@ int boost_init(boost_ctx **out, const uint8_t *d_images, const uint8_t *d_labels
  * over the union), so training continues as from a fresh boost_init.  The
  * paper's case for a distributed trainer is fast retraining when the
  * training set changes (Abstract, Section 1.1).  The old windows' integral
- * images are copied.  For m <= 512 new windows and a union of at most 15,360,
- * the old windows' value order is reused: only the new windows are put in
- * order and merged into each feature's order.  Any other union is sorted in
- * full, which is faster there (the merge still evaluates every window).
+ * images are copied.  For m <= 256 new windows and a union of 7,169 to
+ * 15,360, the old windows' value order is reused: only the new windows are
+ * put in order and merged into each feature's order.  Any other union is
+ * sorted in full, which is faster there (the merge still evaluates every
+ * window).
  *   c              a prepared context (not modified; it stays valid).
  *   d_images       m new windows, window_h x window_w uint8 row-major (device).
  *   d_labels       m labels 0/1 (device).

@@ -154,7 +154,8 @@ int setup_job(JobHost& h, char* ws, int64_t n, const boost_feature_set* fs, cons
         const JobDev& old = *ext->old;
         if ((rc = extend_ii_launch(jd, old, d_images, s)) != BOOST_OK) return rc;
         const int64_t lm = st.n_pos - ext->l0;
-        h.merged = n <= kMergeMaxN && n - old.g.n <= kMergeMaxM && old.g.narrow && old.g.lanes == jd.g.lanes;
+        h.merged = n > kMergeMinN && n <= kMergeMaxN && n - old.g.n <= kMergeMaxM && old.g.narrow &&
+                   old.g.lanes == jd.g.lanes;
         if (h.merged) rc = merge_launch(jd, h.sorder, old.keys, old.g, (int)ext->l0, (int)lm, num_cu, s);
         else rc = sort_launch(jd, h.sorder, h.scratch, h.defer, num_cu, s);
         if (rc != BOOST_OK) return rc;

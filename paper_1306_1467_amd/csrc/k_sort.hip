@@ -667,7 +667,7 @@ __global__ __launch_bounds__(NT) void k_sort_cnt(JobDev jd, const uint32_t* __re
 // the new windows are sorted, and the two ordered lists are merged.
 //   1. the union's values of the feature (one per window, as in k_sort_cnt)
 //      and its packed words in index order;
-//   2. the new windows' words in order (m <= 512), each ranked by counting
+//   2. the new windows' words in order (m <= 256), each ranked by counting
 //      the new words below it;
 //   3. the old windows' words in the old order (decoded from the old keys,
 //      each old index moved to its union index; the move keeps their order);
@@ -685,12 +685,11 @@ struct MergeArgs {
     int32_t nb_off;          // LDS byte offset of the new words in index order (16-byte aligned)
 };
 
-// C: window slots a thread holds (n <= 1024 C).  The new windows (m <= 512)
+// C: window slots a thread holds (n <= 1024 C).  The new windows (m <= 256)
 // are put in order by counting: their words are gathered into one array, and
 // each new word's rank among them is the number of words below it (one pass
 // over the m words, four a read; the counting-sort passes cost more than
-// this at such sizes, and more than sorting the whole union once m passes
-// about 512).
+// this at such sizes).
 template <int C>
 __global__ __launch_bounds__(1024) void k_merge(JobDev jd, const uint32_t* __restrict__ ftab,
                                                const uint32_t* __restrict__ sorder, MergeArgs ma) {
@@ -807,7 +806,7 @@ int merge_launch(const JobDev& jd, const uint32_t* sorder, const uint4* old_keys
     const int64_t n = jd.g.n;
     const int n0 = (int)og.n, m = (int)(n - og.n);
     if (n > kMergeMaxN || m < 1 || m > kMergeMaxM || !og.narrow) {
-        set_error("merge: at most 512 new windows, a union of at most 15,360, narrow old keys");
+        set_error("merge: at most 256 new windows, a union of at most 15,360, narrow old keys");
         return BOOST_E_INVALID;
     }
     MergeArgs ma;

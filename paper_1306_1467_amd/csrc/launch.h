@@ -38,11 +38,16 @@ struct JobHost {
 // A prepared job that a new job extends: the new job's windows are the old
 // job's (in its caller order) followed by the new ones.
 struct ExtendSrc { const JobDev* old; int64_t l0; };
-// A union of at most kMergeMaxN windows that adds at most kMergeMaxM merges
-// the old keys with the sorted new windows; any other is sorted in full
-// (faster there: the merge still evaluates every window).
+// A union of more than kMergeMinN and at most kMergeMaxN windows that adds
+// at most kMergeMaxM merges the old keys with the sorted new windows; any
+// other is sorted in full, which is faster there: the merge still evaluates
+// every window, its ranking of the new windows grows as m^2, and below
+// kMergeMinN the sort's smaller workgroup shapes beat its 1,024 x 11 slots
+// (measured crossovers: about 250 new windows at 10,000 and 14,500 old ones;
+// none at 2,000).
+constexpr int64_t kMergeMinN = 1024 * 7;
 constexpr int64_t kMergeMaxN = 1024 * 15;
-constexpr int64_t kMergeMaxM = 512;
+constexpr int64_t kMergeMaxM = 256;
 int check_job_args(int64_t n, const boost_feature_set* fs, const boost_options* o);
 size_t job_bytes(int64_t n, const boost_feature_set* fs);
 // ext == NULL: a job of d_images / d_labels (n windows).  Otherwise the union
