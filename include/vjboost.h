@@ -78,8 +78,10 @@ typedef struct {
  *                          dominates the added weight) collects each
  *                          addition's exact rounding error in an FP32
  *                          compensation term, folded back into the sum every
- *                          16 keys; candidates (the prefix s + c) are
- *                          compared in FP64.
+ *                          16 keys; candidates are compared in FP64 (the
+ *                          prefix s + c at the last key of each 8-key unit,
+ *                          and for each earlier key the next key's candidate
+ *                          minus the next key's weight).
  *   BOOST_PREC_FP64        FP64 weights and FP64 running sums (n <= 20000:
  *                          the table must fit in LDS).
  *   BOOST_PREC_FP32_WIDE   FP32 weights accumulated in FP64.  For weights
