@@ -119,9 +119,10 @@ template <> struct LaneAcc<BOOST_PREC_FP32_KAHAN> {
     // compensated sum at its key.  That is one convert and one FP64
     // operation per key, plus two per unit.  Each candidate is masked by an
     // integer OR of the all-ones pattern into its high word (a quiet NaN,
-    // which the maximum and minimum skip); the pattern is taken from the
-    // key's run-end bit (bit 0 of its dword for the low key, bit 1 or 16 for
-    // the high one) where it is used, to keep few registers live.
+    // which the maximum and minimum skip) where the key ends no run; the
+    // pattern is taken from the key's no-split bit (bit 0 of its dword for
+    // the low key, bit 1 or 16 for the high one) where it is used, to keep
+    // few registers live.
     template <bool NARROW>
     __device__ __forceinline__ void unit8(const float* w, const uint32_t* d) {
 #pragma unroll
