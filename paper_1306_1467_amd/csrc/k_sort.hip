@@ -109,21 +109,35 @@ __device__ __forceinline__ void unit_keys_w32(const KeyGeom& g, const uint32_t* 
         const int rn = 8 * u + 8;
         const uint32_t w[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, s[rn < n ? rn : n - 1]};
         uint32_t dw[4];
+        if (rn < n) {   // a unit followed by more windows: no bound checks
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            uint32_t ix[2], fl[2];
+            for (int h = 0; h < 4; ++h) {
+                uint32_t ix[2], fl[2];
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int q = 2 * h + e, r = 8 * u + q;
-                if (r < n) {
+                for (int e = 0; e < 2; ++e) {
+                    const int q = 2 * h + e;
                     ix[e] = w[q] & imask;
-                    fl[e] = (r == n - 1) || ((w[q] >> shift) != (w[q + 1] >> shift));
-                } else {
-                    ix[e] = (uint32_t)n;   // padding key: zero-weight table slot, no split
-                    fl[e] = 0;
+                    fl[e] = (w[q] >> shift) != (w[q + 1] >> shift);
                 }
+                dw[h] = encode_pair(g.narrow, ix[0], fl[0], ix[1], fl[1]);
             }
-            dw[h] = encode_pair(g.narrow, ix[0], fl[0], ix[1], fl[1]);
+        } else {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                uint32_t ix[2], fl[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int q = 2 * h + e, r = 8 * u + q;
+                    if (r < n) {
+                        ix[e] = w[q] & imask;
+                        fl[e] = (r == n - 1) || ((w[q] >> shift) != (w[q + 1] >> shift));
+                    } else {
+                        ix[e] = (uint32_t)n;   // padding key: zero-weight table slot, no split
+                        fl[e] = 0;
+                    }
+                }
+                dw[h] = encode_pair(g.narrow, ix[0], fl[0], ix[1], fl[1]);
+            }
         }
         out[k] = make_uint4(dw[0], dw[1], dw[2], dw[3]);
     }
